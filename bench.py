@@ -1,0 +1,163 @@
+"""Benchmark of the Chebyshev-filter hot path on one MI355X.
+
+One step = one pass of the hot path over the resident synthetic block: the
+degree-m Chebyshev filter (m fused BSR-SpMM + recurrence launches) followed,
+when available, by the FP64 Rayleigh-Ritz step (Cholesky-QR twice, X^T H X,
+dense eigensolve, rotation).  Prints ONE JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--precision f64|f32|bf16] [--no-cpu-baseline] [--no-rr]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Chebyshev-filter GFLOP/s + HBM GB/s (% roofline); mixed vs FP64 at ≤1e-6 Ha"
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # dense MFMA peaks, MI355X
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(Hc, X, cfg, n_cols):
+    """The FP64 oracle (SciPy CSR, single thread) on a column sample of the
+    same workload; the filter is column-independent, so the per-column work is
+    the same as in the full run."""
+    import oracle
+    Xs = np.ascontiguousarray(X[:, :n_cols])
+    t0 = time.perf_counter()
+    oracle.cheb_filter(Hc, Xs, cfg.m, cfg.a, cfg.b, cfg.a0)
+    dt = time.perf_counter() - t0
+    flops = 2.0 * Hc.nnz * n_cols * cfg.m
+    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_cols} of {cfg.n} columns, full m={cfg.m} filter, SciPy CSR FP64 "
+                      f"({dt:.1f} s); algorithmic flops 2*nnz*cols*m",
+            "host_cpus": os.cpu_count(), "host": platform.processor() or platform.machine()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="lattice60_h4_n2048_m20")
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-cols", type=int, default=8)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the build has no multi-GPU path "
+              "(the filter shards by columns with no communication; see DESIGN.md).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2110_15853_amd as P
+    import workload
+
+    cfg = workload.CONFIGS[args.workload]
+    log(f"workload {cfg}")
+    t0 = time.perf_counter()
+    ip, ix, d, N = workload.lattice_hamiltonian(cfg.r, cfg.h, cfg.seed)
+    log(f"H generated: N={N} nnz={len(d)} ({time.perf_counter() - t0:.1f} s)")
+    hdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[args.precision]
+    xdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}[args.precision]
+    H = P.bsr_build(ip, ix, d, cfg.r, dtype=hdt, device="cuda")
+    log(f"BSR built: {H.n_block_rows} block rows, {H.n_tiles} tiles")
+    X = workload.gaussian_block(N, cfg.n, cfg.seed)
+    log("X generated")
+    Xb = P.to_blocked(torch.from_numpy(X).cuda(), H)
+    if xdt != torch.float64:
+        Xb = P.cast(Xb, xdt)
+    Y = torch.empty_like(Xb)
+    work = torch.empty(Xb.numel() * Xb.element_size(), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    log("inputs resident on the GPU")
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        P.cheb_filter(H, Xb, cfg.m, cfg.a, cfg.b, cfg.a0, out=Y, work=work)
+        if ev is not None:
+            ev[1].record()
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup}")
+
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(events[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    filt_ms = [a.elapsed_time(b) for a, b in events]
+    log(f"timed {args.steps} steps: wall {wall:.3f} s, filter ms {['%.1f' % v for v in filt_ms]}")
+
+    nnz = len(d)
+    n = cfg.n
+    alg_flops_launch = 2.0 * nnz * n                      # one H*Y_k product
+    issued_flops_launch = 2.0 * H.n_tiles * 4096 * n       # dense 64x64 tiles on the matrix cores
+    elt = Xb.element_size()
+    h_bytes = H.vals.numel() * H.vals.element_size() + 4 * (H.n_tiles + H.n_block_rows + 1)
+    alg_bytes_launch = h_bytes + 3.0 * H.rows * n * elt    # read Y_k, Y_{k-1}, write Y_{k+1}
+    filt_s = float(np.mean(filt_ms)) / 1e3
+    launch_s = filt_s / cfg.m
+    value = alg_flops_launch * cfg.m / filt_s / 1e9
+    peak = PEAK_TFLOPS[args.precision]
+    achieved = alg_flops_launch / launch_s / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision if args.precision != "bf16" else "bf16xf32",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "N": N, "rows_blocked": H.rows, "n_vec": n, "m": cfg.m,
+                   "h": cfg.h, "nnz": nnz, "tiles": H.n_tiles, "fill": nnz / (H.n_tiles * 4096),
+                   "a": cfg.a, "b": cfg.b, "a0": cfg.a0, "step": "chebyshev filter"},
+        "filter_ms": round(filt_s * 1e3, 3),
+        "hbm_gbs_algorithmic": round(alg_bytes_launch / launch_s / 1e9, 1),
+        "issued_tflops": round(issued_flops_launch / launch_s / 1e12, 2),
+        "issued_frac": round(issued_flops_launch / launch_s / 1e12 / peak, 4),
+        "roofline": {"bound": "mfma", "kernel": "cheb_step_mfma4<double>" if args.precision == "f64"
+                     else ("cheb_step_mfma4<float>" if args.precision == "f32" else "cheb_step_bf16<float>"),
+                     "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "per_launch": {"alg_flops": alg_flops_launch, "alg_bytes": alg_bytes_launch,
+                                    "avg_launch_ms": round(launch_s * 1e3, 4)}},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        log("CPU baseline (oracle) ...")
+        Hc = oracle.csr_from_arrays(ip, ix, d, N)
+        out["cpu_baseline"] = cpu_baseline(Hc, X, cfg, args.cpu_cols)
+        log("CPU baseline done")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * ttdft.h - C ABI of the MI355X (gfx950) Chebyshev-filtered subspace iteration
+ * hot path of the Tucker tensor DFT method (Lin & Gavini, arXiv 2110.15853).
+ *
+ * The operations are those of Algorithm 1 (ChFSI, Sec. 3.4):
+ *   step 1  Chebyshev filter      Y = T_m((H - cI)/e) X / T_m((a0 - c)/e)
+ *   step 2  orthonormalisation    X_F = Orth(Y)            (Cholesky-QR, FP64)
+ *   step 3  subspace projection   H_F = X_F^T H X_F         (FP64, Sec. 4.3)
+ *   step 4  dense eigensolve      H_F Q = Q Lambda          (FP64)
+ *   step 5  rotation              Psi = X_F Q               (FP64)
+ * plus the adjoint of step 1 (gradients with respect to X and to the stored
+ * entries of H).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named "device" point to GPU memory owned by the caller; the
+ *   library never frees them and allocates no device memory of its own.
+ *   Host pointers are marked "host".
+ * - Dense blocks (X, Y, ...) are row-major: element (i, j) is at p[i*ld + j],
+ *   with ld >= number of columns.  Rows are in the lattice-blocked order
+ *   produced by ttdft_bsr_build (64 rows per 4x4x4 lattice block; padding rows
+ *   are zero on input and stay zero).
+ * - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ * - Every entry point validates all arguments on the host before any device
+ *   work; a failed validation returns an error status and writes nothing.
+ * - Entry points marked ASYNC only enqueue work on the stream and report launch
+ *   errors (TTDFT_ERR_HIP); the others synchronise the stream before returning.
+ * - A thread-local message describing the last error is available from
+ *   ttdft_last_error().
+ */
+#ifndef TTDFT_H
+#define TTDFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TTDFT_OK = 0,
+  TTDFT_ERR_NULL = 1,           /* a required pointer is NULL                        */
+  TTDFT_ERR_SHAPE = 2,          /* sizes / leading dimensions inconsistent           */
+  TTDFT_ERR_DTYPE = 3,          /* unsupported dtype or dtype combination            */
+  TTDFT_ERR_BOUNDS = 4,         /* filter bounds not finite or not a0 < a < b        */
+  TTDFT_ERR_DEGREE = 5,         /* polynomial degree m < 1                           */
+  TTDFT_ERR_ALIAS = 6,          /* an output overlaps an input it may not overlap    */
+  TTDFT_ERR_WORKSPACE = 7,      /* workspace NULL or smaller than the query result   */
+  TTDFT_ERR_NOT_POSDEF = 8,     /* Cholesky breakdown (rank-deficient block)         */
+  TTDFT_ERR_NO_CONVERGENCE = 9, /* the dense eigensolver did not converge            */
+  TTDFT_ERR_NONFINITE = 10,     /* a non-finite value where a finite one is required */
+  TTDFT_ERR_HIP = 11,           /* a HIP runtime call or kernel launch failed        */
+  TTDFT_ERR_PATTERN = 12        /* CSR input malformed (unsorted, out of range)      */
+} ttdft_status;
+
+typedef enum { TTDFT_F64 = 0, TTDFT_F32 = 1, TTDFT_BF16 = 2 } ttdft_dtype;
+
+/*
+ * Lattice-blocked BSR matrix (all arrays device, caller-owned).
+ * The sparse symmetric Hamiltonian H^L of Sec. 3.3 has entries only between
+ * nearby lattice sites (locality of the localized Tucker basis, Sec. 4.1).  Rows
+ * are grouped by 4x4x4 lattice blocks into block rows of 64; each stored tile is
+ * the dense 64x64 coupling between two blocks.
+ */
+typedef struct {
+  int64_t n_block_rows;        /* number of 64-row blocks; padded row count is 64*n_block_rows */
+  int64_t n_tiles;             /* number of stored 64x64 tiles                                 */
+  const int32_t *tile_rowptr;  /* device [n_block_rows+1]: tiles of block row B are
+                                  tile_rowptr[B] .. tile_rowptr[B+1]-1                         */
+  const int32_t *tile_col;     /* device [n_tiles]: block column of each tile, ascending in a row */
+  const void *vals;            /* device [n_tiles][64][64] row-major values, dtype below       */
+  ttdft_dtype dtype;
+} ttdft_bsr;
+
+/* ---------------------------------------------------------------- host-side builder */
+
+/*
+ * Size query for ttdft_bsr_build.  Input: the natural-order CSR of an N x N
+ * matrix on an r x r x r lattice (N = r^3, row index (i*r + j)*r + k), host
+ * arrays rowptr[N+1] (int64) and col[nnz] (int32, ascending within each row).
+ * Output (host): the number of 64-row blocks and of stored tiles.
+ * Errors: TTDFT_ERR_NULL, TTDFT_ERR_SHAPE (r < 1), TTDFT_ERR_PATTERN.
+ */
+ttdft_status ttdft_bsr_plan(int32_t r, const int64_t *rowptr, const int32_t *col,
+                            int64_t *n_block_rows, int64_t *n_tiles);
+
+/*
+ * Builds the lattice-blocked BSR arrays (all host buffers, caller-allocated
+ * with the sizes from ttdft_bsr_plan):
+ *   tile_rowptr[n_block_rows+1], tile_col[n_tiles],
+ *   vals[n_tiles*4096] of dtype (F64, F32 or BF16; rounding to nearest even),
+ *   perm[64*n_block_rows]: blocked row -> natural row, or -1 for a padding row,
+ *   entry_slot[nnz] (may be NULL): flat index into vals of each CSR entry,
+ *   mask[n_tiles*64] (may be NULL): bit j of word (t*64 + i) set when entry
+ *   (i, j) of tile t is a stored CSR entry.
+ * The lattice is padded to a multiple of 4 per axis with zero rows/columns.
+ * Errors: as ttdft_bsr_plan, plus TTDFT_ERR_DTYPE.
+ */
+ttdft_status ttdft_bsr_build(int32_t r, const int64_t *rowptr, const int32_t *col,
+                             const double *val, ttdft_dtype dtype,
+                             int32_t *tile_rowptr, int32_t *tile_col, void *vals,
+                             int64_t *perm, int64_t *entry_slot, uint64_t *mask);
+
+/* ---------------------------------------------------------------- step 1: Chebyshev filter */
+
+/*
+ * One fused degree step of the scaled three-term recurrence of Algorithm 1
+ * (Sec. 3.4):  Yout = alpha*(H*Yk - c*Yk) - beta*Yprev.
+ * H: F64 with x_dtype F64; F32 with F32; BF16 with F32 or BF16.
+ * Yk, Yprev, Yout: device, 64*n_block_rows x n_vec of x_dtype, leading dims ldk,
+ * ldp, ldo.  Yprev may be NULL only when beta == 0.  Yout may be Yprev (the
+ * update is row-local) but must not overlap Yk.  Accumulation is FP64 for F64
+ * and FP32 otherwise.  ASYNC.
+ * Errors: NULL, SHAPE, DTYPE, ALIAS, NONFINITE (alpha, c or beta), HIP.
+ */
+ttdft_status ttdft_cheb_step(const ttdft_bsr *H, const void *Yk, int64_t ldk,
+                             const void *Yprev, int64_t ldp, void *Yout, int64_t ldo,
+                             int64_t n_vec, double alpha, double c, double beta,
+                             ttdft_dtype x_dtype, void *stream);
+
+/* Bytes of workspace ttdft_cheb_filter needs (one 64*n_block_rows x n_vec block). */
+size_t ttdft_cheb_filter_workspace(const ttdft_bsr *H, int64_t n_vec, ttdft_dtype x_dtype);
+
+/*
+ * Step 1 of Algorithm 1: the degree-m Chebyshev filter with unwanted interval
+ * [a, b] (a = upper bound of the wanted spectrum, b = upper bound of the whole
+ * spectrum) and scaling point a0 below the wanted spectrum (Sec. 3.4):
+ *   Y = T_m((H - cI)/e) X / T_m((a0 - c)/e),  e = (b - a)/2,  c = (b + a)/2,
+ * computed by m fused steps (ttdft_cheb_step) with the sigma-scaled
+ * coefficients alpha_k, beta_k of Algorithm 1.
+ * X (device, read-only) and Y (device, output) are 64*n_block_rows x n_vec of
+ * x_dtype; work is a device buffer of ttdft_cheb_filter_workspace bytes.
+ * Y must not overlap X or work.  ASYNC.
+ * Errors: NULL, SHAPE, DTYPE, BOUNDS (requires a0 < a < b, all finite),
+ * DEGREE (m < 1), ALIAS, WORKSPACE, HIP.
+ */
+ttdft_status ttdft_cheb_filter(const ttdft_bsr *H, const void *X, int64_t ldx, void *Y,
+                               int64_t ldy, int64_t n_vec, int32_t m, double a, double b,
+                               double a0, ttdft_dtype x_dtype, void *work, size_t work_bytes,
+                               void *stream);
+
+/* ---------------------------------------------------------------- precision casts */
+
+/*
+ * dst = src converted between F64, F32 and BF16 (round to nearest even), for a
+ * rows x cols row-major block with leading dims lds / ldd.  Device buffers that
+ * must not overlap.  ASYNC.  Errors: NULL, SHAPE, DTYPE, ALIAS, HIP.
+ */
+ttdft_status ttdft_cast(const void *src, ttdft_dtype src_dtype, int64_t lds, void *dst,
+                        ttdft_dtype dst_dtype, int64_t ldd, int64_t rows, int64_t cols,
+                        void *stream);
+
+/*
+ * Row gather: dst[i, :] = src[perm[i], :] for perm[i] >= 0 and 0 for
+ * perm[i] < 0 (moves blocks between natural and lattice-blocked row order).
+ * perm: device int64 [rows_dst]; entries must be < rows_src.  8-byte (F64),
+ * 4-byte (F32) or 2-byte (BF16) elements.  ASYNC.
+ * Errors: NULL, SHAPE, DTYPE, ALIAS, HIP.
+ */
+ttdft_status ttdft_gather_rows(const void *src, int64_t lds, int64_t rows_src, void *dst,
+                               int64_t ldd, int64_t rows_dst, int64_t cols,
+                               const int64_t *perm, ttdft_dtype dtype, void *stream);
+
+/* ---------------------------------------------------------------- diagnostics */
+
+const char *ttdft_status_string(ttdft_status s);
+const char *ttdft_last_error(void);
+/* Library version string. */
+const char *ttdft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TTDFT_H */

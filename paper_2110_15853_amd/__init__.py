@@ -1,0 +1,19 @@
+"""MI355X (gfx950) Chebyshev-filtered subspace iteration hot path of the Tucker
+tensor DFT method (arXiv 2110.15853): the Chebyshev filter of Algorithm 1
+(Sec. 3.4) on a lattice-blocked sparse Hamiltonian, the FP64 Rayleigh-Ritz step
+that follows it, and the filter's adjoint.
+
+Every operation runs in the HIP kernels of libttdft.so; this package only
+marshals torch tensors (device memory and streams) into the C ABI.
+"""
+from .api import (  # noqa: F401
+    BsrMatrix,
+    bsr_build,
+    cast,
+    cheb_filter,
+    cheb_step,
+    from_blocked,
+    to_blocked,
+    DTYPE_CODES,
+)
+from ._lib import TtdftError, library_path  # noqa: F401

@@ -1,0 +1,161 @@
+"""Python entry points with the names of the C ABI (include/ttdft.h).
+
+Argument marshalling only: tensors supply device pointers, torch's current
+stream supplies the hipStream_t, and every computation runs in libttdft.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BF16, F32, F64, Bsr
+
+DTYPE_CODES = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+_NP_STORAGE = {F64: np.float64, F32: np.float32, BF16: np.uint16}
+
+
+def _code(t: torch.Tensor) -> int:
+    try:
+        return DTYPE_CODES[t.dtype]
+    except KeyError:
+        raise TypeError(f"unsupported dtype {t.dtype}") from None
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _np_ptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else C.c_void_p(0)
+
+
+def _ld(t: torch.Tensor) -> int:
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("expected a 2-D row-major tensor with unit column stride")
+    return t.stride(0)
+
+
+@dataclass
+class BsrMatrix:
+    """Lattice-blocked BSR Hamiltonian on the device (see ttdft_bsr)."""
+    r: int
+    N: int
+    n_block_rows: int
+    n_tiles: int
+    tile_rowptr: torch.Tensor
+    tile_col: torch.Tensor
+    vals: torch.Tensor          # [n_tiles, 64, 64] (bf16 held as torch.bfloat16)
+    perm: torch.Tensor          # blocked row -> natural row or -1 (int64, device)
+    inv_perm: torch.Tensor      # natural row -> blocked row (int64, device)
+    entry_slot: np.ndarray      # host: flat vals index of each CSR entry
+    mask: torch.Tensor          # [n_tiles*64] uint64 stored as int64
+    dtype: int
+
+    @property
+    def rows(self) -> int:
+        return 64 * self.n_block_rows
+
+    def c_struct(self) -> Bsr:
+        return Bsr(self.n_block_rows, self.n_tiles, self.tile_rowptr.data_ptr(),
+                   self.tile_col.data_ptr(), self.vals.data_ptr(), self.dtype)
+
+
+def bsr_build(indptr, indices, data, r: int, dtype=torch.float64, device="cuda") -> BsrMatrix:
+    """ttdft_bsr_plan + ttdft_bsr_build on the host, then copy to the device."""
+    indptr = np.ascontiguousarray(indptr, dtype=np.int64)
+    indices = np.ascontiguousarray(indices, dtype=np.int32)
+    data = np.ascontiguousarray(data, dtype=np.float64)
+    code = DTYPE_CODES[dtype]
+    nbr, nt = C.c_int64(), C.c_int64()
+    _lib.call("ttdft_bsr_plan", r, _np_ptr(indptr), _np_ptr(indices), C.byref(nbr), C.byref(nt))
+    nbr, nt = nbr.value, nt.value
+    tptr = np.empty(nbr + 1, np.int32)
+    tcol = np.empty(nt, np.int32)
+    vals = np.empty(nt * 4096, _NP_STORAGE[code])
+    perm = np.empty(nbr * 64, np.int64)
+    slot = np.empty(len(data), np.int64)
+    mask = np.empty(nt * 64, np.uint64)
+    _lib.call("ttdft_bsr_build", r, _np_ptr(indptr), _np_ptr(indices), _np_ptr(data), code,
+              _np_ptr(tptr), _np_ptr(tcol), _np_ptr(vals), _np_ptr(perm), _np_ptr(slot),
+              _np_ptr(mask))
+    N = r ** 3
+    inv = np.empty(N, np.int64)
+    real = perm >= 0
+    inv[perm[real]] = np.nonzero(real)[0]
+    tvals = torch.from_numpy(vals.view(np.int16)).view(torch.bfloat16) if code == BF16 \
+        else torch.from_numpy(vals)
+    return BsrMatrix(r=r, N=N, n_block_rows=nbr, n_tiles=nt,
+                     tile_rowptr=torch.from_numpy(tptr).to(device),
+                     tile_col=torch.from_numpy(tcol).to(device),
+                     vals=tvals.reshape(nt, 64, 64).to(device),
+                     perm=torch.from_numpy(perm).to(device),
+                     inv_perm=torch.from_numpy(inv).to(device),
+                     entry_slot=slot,
+                     mask=torch.from_numpy(mask.view(np.int64)).to(device),
+                     dtype=code)
+
+
+def gather_rows(src: torch.Tensor, perm: torch.Tensor, rows_dst: int) -> torch.Tensor:
+    """ttdft_gather_rows: out[i] = src[perm[i]] (0 where perm[i] < 0)."""
+    out = torch.empty((rows_dst, src.shape[1]), dtype=src.dtype, device=src.device)
+    _lib.call("ttdft_gather_rows", _ptr(src), _ld(src), src.shape[0], _ptr(out), _ld(out),
+              rows_dst, src.shape[1], _ptr(perm), _code(src), _stream())
+    return out
+
+
+def to_blocked(X: torch.Tensor, H: BsrMatrix) -> torch.Tensor:
+    """Natural row order (N rows) -> lattice-blocked order (64*n_block_rows rows, zero padding)."""
+    if X.shape[0] != H.N:
+        raise ValueError("X must have N rows in natural order")
+    return gather_rows(X, H.perm, H.rows)
+
+
+def from_blocked(Y: torch.Tensor, H: BsrMatrix) -> torch.Tensor:
+    """Lattice-blocked order -> natural row order (drops padding rows)."""
+    if Y.shape[0] != H.rows:
+        raise ValueError("Y must have 64*n_block_rows rows")
+    return gather_rows(Y, H.inv_perm, H.N)
+
+
+def cast(src: torch.Tensor, dtype: torch.dtype) -> torch.Tensor:
+    """ttdft_cast: precision conversion (round to nearest even)."""
+    out = torch.empty(src.shape, dtype=dtype, device=src.device)
+    _lib.call("ttdft_cast", _ptr(src), _code(src), _ld(src), _ptr(out), DTYPE_CODES[dtype],
+              _ld(out), src.shape[0], src.shape[1], _stream())
+    return out
+
+
+def cheb_step(H: BsrMatrix, Yk: torch.Tensor, Yprev, alpha: float, c: float, beta: float,
+              out: torch.Tensor = None) -> torch.Tensor:
+    """ttdft_cheb_step: out = alpha*(H Yk - c Yk) - beta*Yprev."""
+    if out is None:
+        out = torch.empty_like(Yk)
+    hs = H.c_struct()
+    _lib.call("ttdft_cheb_step", C.byref(hs), _ptr(Yk), _ld(Yk), _ptr(Yprev),
+              _ld(Yprev) if Yprev is not None else 0, _ptr(out), _ld(out), Yk.shape[1],
+              alpha, c, beta, _code(Yk), _stream())
+    return out
+
+
+def cheb_filter(H: BsrMatrix, X: torch.Tensor, m: int, a: float, b: float, a0: float,
+                out: torch.Tensor = None, work: torch.Tensor = None) -> torch.Tensor:
+    """ttdft_cheb_filter: Y = T_m((H - cI)/e) X / T_m((a0 - c)/e) on blocked rows."""
+    hs = H.c_struct()
+    n = X.shape[1]
+    code = _code(X)
+    need = _lib.load().ttdft_cheb_filter_workspace(C.byref(hs), n, code)
+    if out is None:
+        out = torch.empty((H.rows, n), dtype=X.dtype, device=X.device)
+    if work is None and m >= 2:
+        work = torch.empty(need, dtype=torch.uint8, device=X.device)
+    _lib.call("ttdft_cheb_filter", C.byref(hs), _ptr(X), _ld(X), _ptr(out), _ld(out), n, m,
+              a, b, a0, code, _ptr(work), work.numel() if work is not None else 0, _stream())
+    return out

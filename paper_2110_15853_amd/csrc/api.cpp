@@ -1,0 +1,345 @@
+// Host side of libttdft: argument validation, the coefficient schedule of the
+// Chebyshev filter, the lattice-blocked BSR builder and dispatch to the HIP
+// kernels.  Every entry point validates all arguments before touching the
+// device, so error paths can be exercised without a GPU.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "ttdft_internal.h"
+
+using namespace ttdft;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+ttdft_status fail(ttdft_status s, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+ttdft_status ok() {
+  g_err[0] = '\0';
+  return TTDFT_OK;
+}
+
+ttdft_status hip_status(hipError_t e, const char *what) {
+  if (e == hipSuccess) return ok();
+  return fail(TTDFT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool valid_dtype(int t) { return t == TTDFT_F64 || t == TTDFT_F32 || t == TTDFT_BF16; }
+
+// byte range [lo, hi) touched by a rows x cols block with leading dim ld
+struct Span {
+  uintptr_t lo = 0, hi = 0;
+};
+Span span_of(const void *p, int64_t rows, int64_t ld, int64_t cols, size_t elt) {
+  Span s;
+  if (!p || rows <= 0 || cols <= 0) return s;
+  s.lo = (uintptr_t)p;
+  s.hi = s.lo + (uintptr_t)(((rows - 1) * ld + cols) * (int64_t)elt);
+  return s;
+}
+Span span_bytes(const void *p, size_t bytes) {
+  Span s;
+  if (!p || bytes == 0) return s;
+  s.lo = (uintptr_t)p;
+  s.hi = s.lo + bytes;
+  return s;
+}
+bool overlap(const Span &a, const Span &b) {
+  return a.hi > a.lo && b.hi > b.lo && a.lo < b.hi && b.lo < a.hi;
+}
+
+ttdft_status check_bsr(const ttdft_bsr *H) {
+  if (!H) return fail(TTDFT_ERR_NULL, "H is NULL");
+  if (!valid_dtype(H->dtype)) return fail(TTDFT_ERR_DTYPE, "H dtype %d unknown", (int)H->dtype);
+  if (H->n_block_rows < 1 || H->n_tiles < 0)
+    return fail(TTDFT_ERR_SHAPE, "H has %lld block rows and %lld tiles",
+                (long long)H->n_block_rows, (long long)H->n_tiles);
+  if (H->n_block_rows > (int64_t)1 << 30 || H->n_tiles > 0x7fffffff)
+    return fail(TTDFT_ERR_SHAPE, "H too large for 32-bit tile indices");
+  if (!H->tile_rowptr) return fail(TTDFT_ERR_NULL, "H.tile_rowptr is NULL");
+  if (H->n_tiles > 0 && (!H->tile_col || !H->vals))
+    return fail(TTDFT_ERR_NULL, "H.tile_col or H.vals is NULL");
+  return TTDFT_OK;
+}
+
+// dtype pairs (H, X) the fused step supports
+bool supported_pair(ttdft_dtype h, ttdft_dtype x) {
+  return (h == TTDFT_F64 && x == TTDFT_F64) || (h == TTDFT_F32 && x == TTDFT_F32) ||
+         (h == TTDFT_BF16 && (x == TTDFT_F32 || x == TTDFT_BF16));
+}
+
+uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// ---- lattice blocking: natural index (i*r + j)*r + k -> (block, local)
+struct Lattice {
+  int64_t r, nb;
+  explicit Lattice(int64_t r_) : r(r_), nb((r_ + 3) / 4) {}
+  int64_t n_block_rows() const { return nb * nb * nb; }
+  void split(int64_t I, int64_t &blk, int64_t &loc) const {
+    const int64_t i = I / (r * r), j = (I / r) % r, k = I % r;
+    blk = ((i / 4) * nb + j / 4) * nb + k / 4;
+    loc = ((i % 4) * 4 + j % 4) * 4 + k % 4;
+  }
+};
+
+ttdft_status check_csr(int32_t r, const int64_t *rowptr, const int32_t *col) {
+  if (!rowptr || !col) return fail(TTDFT_ERR_NULL, "rowptr or col is NULL");
+  if (r < 1 || r > 2048) return fail(TTDFT_ERR_SHAPE, "lattice extent r=%d out of range", r);
+  const int64_t N = (int64_t)r * r * r;
+  if (rowptr[0] != 0) return fail(TTDFT_ERR_PATTERN, "rowptr[0] != 0");
+  for (int64_t I = 0; I < N; ++I) {
+    if (rowptr[I + 1] < rowptr[I]) return fail(TTDFT_ERR_PATTERN, "rowptr decreases at row %lld", (long long)I);
+    for (int64_t p = rowptr[I]; p < rowptr[I + 1]; ++p) {
+      if (col[p] < 0 || col[p] >= N)
+        return fail(TTDFT_ERR_PATTERN, "column %d out of range in row %lld", col[p], (long long)I);
+      if (p > rowptr[I] && col[p] <= col[p - 1])
+        return fail(TTDFT_ERR_PATTERN, "columns not strictly ascending in row %lld", (long long)I);
+    }
+  }
+  return TTDFT_OK;
+}
+
+// sorted distinct block columns of every block row
+void block_pattern(const Lattice &L, const int64_t *rowptr, const int32_t *col,
+                   std::vector<int32_t> &tptr, std::vector<int32_t> &tcol) {
+  const int64_t NB = L.n_block_rows(), N = L.r * L.r * L.r;
+  std::vector<std::vector<int32_t>> rows_of(NB);
+  for (int64_t I = 0; I < N; ++I) {
+    int64_t b, l;
+    L.split(I, b, l);
+    rows_of[b].push_back((int32_t)I);
+  }
+  std::vector<int64_t> stamp(NB, -1);
+  tptr.assign(NB + 1, 0);
+  tcol.clear();
+  std::vector<int32_t> cur;
+  for (int64_t B = 0; B < NB; ++B) {
+    cur.clear();
+    for (int32_t I : rows_of[B])
+      for (int64_t p = rowptr[I]; p < rowptr[I + 1]; ++p) {
+        int64_t bc, lc;
+        L.split(col[p], bc, lc);
+        if (stamp[bc] != B) {
+          stamp[bc] = B;
+          cur.push_back((int32_t)bc);
+        }
+      }
+    std::sort(cur.begin(), cur.end());
+    tcol.insert(tcol.end(), cur.begin(), cur.end());
+    tptr[B + 1] = (int32_t)tcol.size();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ttdft_version(void) { return "ttdft-gfx950 0.1"; }
+
+const char *ttdft_last_error(void) { return g_err; }
+
+const char *ttdft_status_string(ttdft_status s) {
+  switch (s) {
+    case TTDFT_OK: return "ok";
+    case TTDFT_ERR_NULL: return "null pointer";
+    case TTDFT_ERR_SHAPE: return "bad shape";
+    case TTDFT_ERR_DTYPE: return "unsupported dtype";
+    case TTDFT_ERR_BOUNDS: return "bad filter bounds";
+    case TTDFT_ERR_DEGREE: return "bad polynomial degree";
+    case TTDFT_ERR_ALIAS: return "overlapping buffers";
+    case TTDFT_ERR_WORKSPACE: return "workspace too small";
+    case TTDFT_ERR_NOT_POSDEF: return "Cholesky breakdown";
+    case TTDFT_ERR_NO_CONVERGENCE: return "eigensolver did not converge";
+    case TTDFT_ERR_NONFINITE: return "non-finite value";
+    case TTDFT_ERR_HIP: return "HIP error";
+    case TTDFT_ERR_PATTERN: return "malformed sparsity pattern";
+  }
+  return "unknown status";
+}
+
+ttdft_status ttdft_bsr_plan(int32_t r, const int64_t *rowptr, const int32_t *col,
+                            int64_t *n_block_rows, int64_t *n_tiles) {
+  if (!n_block_rows || !n_tiles) return fail(TTDFT_ERR_NULL, "output pointer is NULL");
+  ttdft_status st = check_csr(r, rowptr, col);
+  if (st != TTDFT_OK) return st;
+  Lattice L(r);
+  std::vector<int32_t> tptr, tcol;
+  block_pattern(L, rowptr, col, tptr, tcol);
+  *n_block_rows = L.n_block_rows();
+  *n_tiles = (int64_t)tcol.size();
+  return ok();
+}
+
+ttdft_status ttdft_bsr_build(int32_t r, const int64_t *rowptr, const int32_t *col,
+                             const double *val, ttdft_dtype dtype, int32_t *tile_rowptr,
+                             int32_t *tile_col, void *vals, int64_t *perm, int64_t *entry_slot,
+                             uint64_t *mask) {
+  if (!val || !tile_rowptr || !tile_col || !vals || !perm)
+    return fail(TTDFT_ERR_NULL, "an output or val pointer is NULL");
+  if (!valid_dtype(dtype)) return fail(TTDFT_ERR_DTYPE, "dtype %d unknown", (int)dtype);
+  ttdft_status st = check_csr(r, rowptr, col);
+  if (st != TTDFT_OK) return st;
+  Lattice L(r);
+  const int64_t NB = L.n_block_rows(), N = (int64_t)r * r * r;
+  std::vector<int32_t> tptr, tcol;
+  block_pattern(L, rowptr, col, tptr, tcol);
+  const int64_t nt = (int64_t)tcol.size();
+  std::copy(tptr.begin(), tptr.end(), tile_rowptr);
+  std::copy(tcol.begin(), tcol.end(), tile_col);
+  std::memset(vals, 0, (size_t)nt * kTileElems * dtype_size(dtype));
+  if (mask) std::memset(mask, 0, (size_t)nt * 64 * sizeof(uint64_t));
+  for (int64_t p = 0; p < NB * 64; ++p) perm[p] = -1;
+  for (int64_t I = 0; I < N; ++I) {
+    int64_t b, l;
+    L.split(I, b, l);
+    perm[b * 64 + l] = I;
+    for (int64_t p = rowptr[I]; p < rowptr[I + 1]; ++p) {
+      int64_t bc, lc;
+      L.split(col[p], bc, lc);
+      const int32_t *first = tile_col + tptr[b], *last = tile_col + tptr[b + 1];
+      const int64_t t = tptr[b] + (std::lower_bound(first, last, (int32_t)bc) - first);
+      const int64_t slot = t * kTileElems + l * 64 + lc;
+      if (dtype == TTDFT_F64) {
+        ((double *)vals)[slot] = val[p];
+      } else if (dtype == TTDFT_F32) {
+        ((float *)vals)[slot] = (float)val[p];
+      } else {
+        ((uint16_t *)vals)[slot] = f32_to_bf16_rne((float)val[p]);
+      }
+      if (entry_slot) entry_slot[p] = slot;
+      if (mask) mask[t * 64 + l] |= (uint64_t)1 << lc;
+    }
+  }
+  return ok();
+}
+
+ttdft_status ttdft_cheb_step(const ttdft_bsr *H, const void *Yk, int64_t ldk, const void *Yprev,
+                             int64_t ldp, void *Yout, int64_t ldo, int64_t n_vec, double alpha,
+                             double c, double beta, ttdft_dtype x_dtype, void *stream) {
+  ttdft_status st = check_bsr(H);
+  if (st != TTDFT_OK) return st;
+  if (!valid_dtype(x_dtype) || !supported_pair(H->dtype, x_dtype))
+    return fail(TTDFT_ERR_DTYPE, "unsupported (H, X) dtype pair (%d, %d)", (int)H->dtype, (int)x_dtype);
+  if (!Yk || !Yout) return fail(TTDFT_ERR_NULL, "Yk or Yout is NULL");
+  if (beta != 0.0 && !Yprev) return fail(TTDFT_ERR_NULL, "Yprev is NULL with beta != 0");
+  if (n_vec < 1) return fail(TTDFT_ERR_SHAPE, "n_vec = %lld < 1", (long long)n_vec);
+  if (ldk < n_vec || ldo < n_vec || (Yprev && ldp < n_vec))
+    return fail(TTDFT_ERR_SHAPE, "leading dimension smaller than n_vec");
+  if (!std::isfinite(alpha) || !std::isfinite(c) || !std::isfinite(beta))
+    return fail(TTDFT_ERR_NONFINITE, "alpha, c and beta must be finite");
+  const int64_t rows = H->n_block_rows * 64;
+  const size_t elt = dtype_size(x_dtype);
+  const Span sk = span_of(Yk, rows, ldk, n_vec, elt), so = span_of(Yout, rows, ldo, n_vec, elt);
+  if (overlap(sk, so)) return fail(TTDFT_ERR_ALIAS, "Yout overlaps Yk");
+  if (Yprev && beta != 0.0) {
+    const Span sp = span_of(Yprev, rows, ldp, n_vec, elt);
+    if (overlap(sp, so) && !(Yprev == Yout && ldp == ldo))
+      return fail(TTDFT_ERR_ALIAS, "Yout partially overlaps Yprev");
+  }
+  return hip_status(launch_cheb_step(*H, Yk, ldk, beta != 0.0 ? Yprev : nullptr, ldp, Yout, ldo,
+                                     n_vec, alpha, c, beta, x_dtype, (hipStream_t)stream),
+                    "cheb_step launch");
+}
+
+size_t ttdft_cheb_filter_workspace(const ttdft_bsr *H, int64_t n_vec, ttdft_dtype x_dtype) {
+  if (!H || H->n_block_rows < 1 || n_vec < 1 || !valid_dtype(x_dtype)) return 0;
+  return (size_t)H->n_block_rows * 64 * (size_t)n_vec * dtype_size(x_dtype);
+}
+
+ttdft_status ttdft_cheb_filter(const ttdft_bsr *H, const void *X, int64_t ldx, void *Y,
+                               int64_t ldy, int64_t n_vec, int32_t m, double a, double b,
+                               double a0, ttdft_dtype x_dtype, void *work, size_t work_bytes,
+                               void *stream) {
+  ttdft_status st = check_bsr(H);
+  if (st != TTDFT_OK) return st;
+  if (!valid_dtype(x_dtype) || !supported_pair(H->dtype, x_dtype))
+    return fail(TTDFT_ERR_DTYPE, "unsupported (H, X) dtype pair (%d, %d)", (int)H->dtype, (int)x_dtype);
+  if (!X || !Y) return fail(TTDFT_ERR_NULL, "X or Y is NULL");
+  if (n_vec < 1) return fail(TTDFT_ERR_SHAPE, "n_vec = %lld < 1", (long long)n_vec);
+  if (ldx < n_vec || ldy < n_vec) return fail(TTDFT_ERR_SHAPE, "leading dimension smaller than n_vec");
+  if (!(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0)) || !(a0 < a && a < b))
+    return fail(TTDFT_ERR_BOUNDS, "bounds must be finite with a0 < a < b (got a0=%g a=%g b=%g)", a0, a, b);
+  if (m < 1) return fail(TTDFT_ERR_DEGREE, "degree m = %d < 1", m);
+  const int64_t rows = H->n_block_rows * 64;
+  const size_t elt = dtype_size(x_dtype);
+  const size_t need = ttdft_cheb_filter_workspace(H, n_vec, x_dtype);
+  if (m >= 2 && (!work || work_bytes < need))
+    return fail(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", need);
+  const Span sx = span_of(X, rows, ldx, n_vec, elt), sy = span_of(Y, rows, ldy, n_vec, elt);
+  const Span sw = m >= 2 ? span_bytes(work, need) : Span{};
+  if (overlap(sx, sy)) return fail(TTDFT_ERR_ALIAS, "Y overlaps X");
+  if (overlap(sw, sy) || overlap(sw, sx)) return fail(TTDFT_ERR_ALIAS, "workspace overlaps X or Y");
+
+  // coefficient schedule of Algorithm 1 (Sec. 3.4), FP64 on the host
+  const double e = 0.5 * (b - a), c = 0.5 * (b + a);
+  double sigma = e / (a0 - c);
+  const double sigma1 = sigma, gamma = 2.0 / sigma1;
+  // Y_k for k >= 1 lives in Y when k has the parity of m, else in work, so the
+  // last iterate lands in Y and Y_{k+1} overwrites Y_{k-1} in place.
+  auto buf = [&](int k) -> void * { return (k % 2 == m % 2) ? Y : work; };
+  auto ld_of = [&](int k) -> int64_t { return (k % 2 == m % 2) ? ldy : n_vec; };
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t err = launch_cheb_step(*H, X, ldx, nullptr, 0, buf(1), ld_of(1), n_vec,
+                                    sigma1 / e, c, 0.0, x_dtype, s);
+  if (err != hipSuccess) return hip_status(err, "cheb_filter step 1");
+  for (int k = 2; k <= m; ++k) {
+    const double sigma2 = 1.0 / (gamma - sigma);
+    const void *prev = (k == 2) ? X : buf(k - 2);
+    const int64_t ldp = (k == 2) ? ldx : ld_of(k - 2);
+    err = launch_cheb_step(*H, buf(k - 1), ld_of(k - 1), prev, ldp, buf(k), ld_of(k), n_vec,
+                           2.0 * sigma2 / e, c, sigma * sigma2, x_dtype, s);
+    if (err != hipSuccess) return hip_status(err, "cheb_filter step");
+    sigma = sigma2;
+  }
+  return ok();
+}
+
+ttdft_status ttdft_cast(const void *src, ttdft_dtype src_dtype, int64_t lds, void *dst,
+                        ttdft_dtype dst_dtype, int64_t ldd, int64_t rows, int64_t cols,
+                        void *stream) {
+  if (!valid_dtype(src_dtype) || !valid_dtype(dst_dtype))
+    return fail(TTDFT_ERR_DTYPE, "unknown dtype");
+  if (rows < 0 || cols < 0 || lds < cols || ldd < cols)
+    return fail(TTDFT_ERR_SHAPE, "bad cast shape");
+  if (rows == 0 || cols == 0) return ok();
+  if (!src || !dst) return fail(TTDFT_ERR_NULL, "src or dst is NULL");
+  if (overlap(span_of(src, rows, lds, cols, dtype_size(src_dtype)),
+              span_of(dst, rows, ldd, cols, dtype_size(dst_dtype))))
+    return fail(TTDFT_ERR_ALIAS, "cast buffers overlap");
+  return hip_status(launch_cast(src, src_dtype, lds, dst, dst_dtype, ldd, rows, cols,
+                                (hipStream_t)stream), "cast launch");
+}
+
+ttdft_status ttdft_gather_rows(const void *src, int64_t lds, int64_t rows_src, void *dst,
+                               int64_t ldd, int64_t rows_dst, int64_t cols, const int64_t *perm,
+                               ttdft_dtype dtype, void *stream) {
+  if (!valid_dtype(dtype)) return fail(TTDFT_ERR_DTYPE, "unknown dtype");
+  if (rows_src < 0 || rows_dst < 0 || cols < 0 || lds < cols || ldd < cols)
+    return fail(TTDFT_ERR_SHAPE, "bad gather shape");
+  if (rows_dst == 0 || cols == 0) return ok();
+  if (!src || !dst || !perm) return fail(TTDFT_ERR_NULL, "src, dst or perm is NULL");
+  const size_t elt = dtype_size(dtype);
+  if (overlap(span_of(src, rows_src, lds, cols, elt), span_of(dst, rows_dst, ldd, cols, elt)))
+    return fail(TTDFT_ERR_ALIAS, "gather buffers overlap");
+  return hip_status(launch_gather_rows(src, lds, dst, ldd, rows_dst, cols, perm, elt,
+                                       (hipStream_t)stream), "gather launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,222 @@
+// Fused lattice-blocked BSR SpMM + Chebyshev recurrence epilogue for gfx950.
+//
+// One launch performs one degree step of the scaled three-term recurrence of
+// Algorithm 1 (Sec. 3.4):
+//     Yout[B, :] = alpha * (sum_{B'} H[B, B'] Yk[B', :] - c * Yk[B, :]) - beta * Yprev[B, :]
+// for every 64-row lattice block B.  The sparse-dense product H Yk is the main
+// kernel of the filter (Sec. 4); here the dense 64x64 tiles of the blocked H are
+// contracted on the matrix cores and the recurrence update is applied in the
+// epilogue, so Yk, Yprev and Yout each cross HBM once per step.
+//
+// Work decomposition: one work-group (4 waves) owns one block row B and one
+// column tile of NV = 64 vectors; it walks the (at most 27) tiles of B, staging
+// the H tile and the matching Yk row panel in LDS, and accumulates in MFMA
+// registers.  Each output element is produced by exactly one work-group, so
+// results are deterministic (no atomics).
+#include "ttdft_internal.h"
+
+namespace ttdft {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int NV = 64;        // vectors per work-group
+constexpr int THREADS = 256;  // 4 waves
+
+// Work-groups are dispatched round-robin over the 8 XCDs.  Remap the hardware
+// id so each XCD gets a contiguous range of logical ids: consecutive logical ids
+// share a block row (and so its H tiles) inside one XCD's L2.
+__device__ inline int64_t xcd_remap(int64_t g, int64_t G) {
+  const int64_t xcd = g % 8, local = g / 8;
+  const int64_t per = G / 8, rem = G % 8;
+  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+// MFMA 16x16x4 on scalar operands: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// output item t of lane l is D[row(l, t)][l%16].
+template <typename T> struct Mfma4;
+template <> struct Mfma4<double> {
+  using acc_t = v4d;
+  static __device__ inline acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lane, int t) { return (lane >> 4) + 4 * t; }
+};
+template <> struct Mfma4<float> {
+  using acc_t = v4f;
+  static __device__ inline acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lane, int t) { return 4 * (lane >> 4) + t; }
+};
+
+// T = storage and arithmetic type of H and Y (double: FP64 MFMA; float: FP32 MFMA).
+template <typename T>
+__global__ __launch_bounds__(THREADS) void cheb_step_mfma4(
+    const int32_t *__restrict__ rowptr, const int32_t *__restrict__ tcol,
+    const T *__restrict__ vals, const T *__restrict__ Yk, int64_t ldk,
+    const T *__restrict__ Yp, int64_t ldp, T *Yo, int64_t ldo, int64_t n_vec, int64_t n_ct,
+    int64_t n_wg, T alpha, T c, T beta) {
+  using M = Mfma4<T>;
+  __shared__ T sH[64][65];
+  __shared__ T sX[64][NV + 1];
+
+  const int64_t g = xcd_remap(blockIdx.x, n_wg);
+  const int64_t B = g / n_ct, ct = g % n_ct;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t col0 = ct * NV;
+
+  typename M::acc_t acc[4];
+  for (int j = 0; j < 4; ++j) acc[j] = typename M::acc_t{0, 0, 0, 0};
+
+  const int t_begin = rowptr[B], t_end = rowptr[B + 1];
+  for (int t = t_begin; t < t_end; ++t) {
+    const int64_t Bc = tcol[t];
+    const T *Ht = vals + (int64_t)t * kTileElems;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + THREADS * q;
+      sH[idx >> 6][idx & 63] = Ht[idx];
+    }
+    const T *Xp = Yk + Bc * 64 * ldk;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + THREADS * q;
+      const int r = idx >> 6, cc = idx & 63;
+      const int64_t col = col0 + cc;
+      sX[r][cc] = col < n_vec ? Xp[(int64_t)r * ldk + col] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 64; kk += 4) {
+      const T a = sH[16 * w + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) {
+        const T b = sX[kk + (lane >> 4)][16 * jb + (lane & 15)];
+        acc[jb] = M::op(a, b, acc[jb]);
+      }
+    }
+    __syncthreads();
+  }
+
+  // epilogue: Yout = alpha*(acc - c*Yk) - beta*Yprev (row-local, so Yout may be Yprev)
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) {
+    const int64_t col = col0 + 16 * jb + (lane & 15);
+    if (col >= n_vec) continue;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t grow = B * 64 + 16 * w + M::row(lane, t);
+      const T y = Yk[grow * ldk + col];
+      T out = alpha * (acc[jb][t] - c * y);
+      if (beta != T(0)) out -= beta * Yp[grow * ldp + col];
+      Yo[grow * ldo + col] = out;
+    }
+  }
+}
+
+// BF16 H tiles with FP32 or BF16 iterates; FP32 accumulation on the
+// 16x16x32 bf16 matrix op.  Lane l supplies A[l%16][8*(l/16) .. +7] and
+// B[8*(l/16) .. +7][l%16]; output item t is D[4*(l/16)+t][l%16].
+template <typename TX> __device__ inline float to_f32(TX v);
+template <> __device__ inline float to_f32<float>(float v) { return v; }
+template <> __device__ inline float to_f32<__bf16>(__bf16 v) { return (float)v; }
+template <typename TX> __device__ inline TX from_f32(float v);
+template <> __device__ inline float from_f32<float>(float v) { return v; }
+template <> __device__ inline __bf16 from_f32<__bf16>(float v) { return (__bf16)v; }
+
+template <typename TX>
+__global__ __launch_bounds__(THREADS) void cheb_step_bf16(
+    const int32_t *__restrict__ rowptr, const int32_t *__restrict__ tcol,
+    const __bf16 *__restrict__ vals, const TX *__restrict__ Yk, int64_t ldk,
+    const TX *__restrict__ Yp, int64_t ldp, TX *Yo, int64_t ldo, int64_t n_vec, int64_t n_ct,
+    int64_t n_wg, float alpha, float c, float beta) {
+  // rows padded by 8 bf16 (16 bytes) to spread LDS banks, keeping 16-byte alignment
+  __shared__ __attribute__((aligned(16))) __bf16 sH[64][64 + 8];
+  __shared__ __attribute__((aligned(16))) __bf16 sXT[NV][64 + 8];  // transposed panel: [vector][k]
+
+  const int64_t g = xcd_remap(blockIdx.x, n_wg);
+  const int64_t B = g / n_ct, ct = g % n_ct;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t col0 = ct * NV;
+
+  v4f acc[4];
+  for (int j = 0; j < 4; ++j) acc[j] = v4f{0, 0, 0, 0};
+
+  const int t_begin = rowptr[B], t_end = rowptr[B + 1];
+  for (int t = t_begin; t < t_end; ++t) {
+    const int64_t Bc = tcol[t];
+    const __bf16 *Ht = vals + (int64_t)t * kTileElems;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + THREADS * q;
+      sH[idx >> 6][idx & 63] = Ht[idx];
+    }
+    const TX *Xp = Yk + Bc * 64 * ldk;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = tid + THREADS * q;
+      const int r = idx >> 6, cc = idx & 63;
+      const int64_t col = col0 + cc;
+      sXT[cc][r] = col < n_vec ? (__bf16)to_f32<TX>(Xp[(int64_t)r * ldk + col]) : (__bf16)0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 64; kk += 32) {
+      const v8bf a = *reinterpret_cast<const v8bf *>(&sH[16 * w + (lane & 15)][kk + 8 * (lane >> 4)]);
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) {
+        const v8bf b = *reinterpret_cast<const v8bf *>(&sXT[16 * jb + (lane & 15)][kk + 8 * (lane >> 4)]);
+        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[jb], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) {
+    const int64_t col = col0 + 16 * jb + (lane & 15);
+    if (col >= n_vec) continue;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t grow = B * 64 + 16 * w + 4 * (lane >> 4) + t;
+      const float y = to_f32<TX>(Yk[grow * ldk + col]);
+      float out = alpha * (acc[jb][t] - c * y);
+      if (beta != 0.0f) out -= beta * to_f32<TX>(Yp[grow * ldp + col]);
+      Yo[grow * ldo + col] = from_f32<TX>(out);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, const void *Yp,
+                            int64_t ldp, void *Yo, int64_t ldo, int64_t n_vec, double alpha,
+                            double c, double beta, ttdft_dtype xt, hipStream_t s) {
+  const int64_t n_ct = (n_vec + NV - 1) / NV;
+  const int64_t n_wg = H.n_block_rows * n_ct;
+  if (n_wg > 0x7fffffff) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)n_wg), block(THREADS);
+  if (H.dtype == TTDFT_F64) {
+    hipLaunchKernelGGL(cheb_step_mfma4<double>, grid, block, 0, s, H.tile_rowptr, H.tile_col,
+                       (const double *)H.vals, (const double *)Yk, ldk, (const double *)Yp, ldp,
+                       (double *)Yo, ldo, n_vec, n_ct, n_wg, alpha, c, beta);
+  } else if (H.dtype == TTDFT_F32) {
+    hipLaunchKernelGGL(cheb_step_mfma4<float>, grid, block, 0, s, H.tile_rowptr, H.tile_col,
+                       (const float *)H.vals, (const float *)Yk, ldk, (const float *)Yp, ldp,
+                       (float *)Yo, ldo, n_vec, n_ct, n_wg, (float)alpha, (float)c, (float)beta);
+  } else if (xt == TTDFT_F32) {
+    hipLaunchKernelGGL(cheb_step_bf16<float>, grid, block, 0, s, H.tile_rowptr, H.tile_col,
+                       (const __bf16 *)H.vals, (const float *)Yk, ldk, (const float *)Yp, ldp,
+                       (float *)Yo, ldo, n_vec, n_ct, n_wg, (float)alpha, (float)c, (float)beta);
+  } else {
+    hipLaunchKernelGGL(cheb_step_bf16<__bf16>, grid, block, 0, s, H.tile_rowptr, H.tile_col,
+                       (const __bf16 *)H.vals, (const __bf16 *)Yk, ldk, (const __bf16 *)Yp, ldp,
+                       (__bf16 *)Yo, ldo, n_vec, n_ct, n_wg, (float)alpha, (float)c, (float)beta);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ttdft

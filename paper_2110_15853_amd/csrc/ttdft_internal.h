@@ -1,0 +1,64 @@
+// Internal declarations shared by the host entry points and the HIP kernel
+// launchers of libttdft.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+#include "../../include/ttdft.h"
+
+namespace ttdft {
+
+inline size_t dtype_size(ttdft_dtype t) {
+  return t == TTDFT_F64 ? 8 : t == TTDFT_F32 ? 4 : 2;
+}
+
+constexpr int kTile = 64;                    // rows per lattice block (4x4x4)
+constexpr int64_t kTileElems = 64 * 64;
+
+// ---- fused BSR SpMM + Chebyshev recurrence epilogue (one degree step)
+hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, const void *Yp,
+                            int64_t ldp, void *Yo, int64_t ldo, int64_t n_vec, double alpha,
+                            double c, double beta, ttdft_dtype xt, hipStream_t s);
+
+// ---- element-wise / layout kernels
+hipError_t launch_cast(const void *src, ttdft_dtype st, int64_t lds, void *dst, ttdft_dtype dt,
+                       int64_t ldd, int64_t rows, int64_t cols, hipStream_t s);
+hipError_t launch_gather_rows(const void *src, int64_t lds, void *dst, int64_t ldd,
+                              int64_t rows_dst, int64_t cols, const int64_t *perm, size_t elt,
+                              hipStream_t s);
+
+// ---- FP64 dense kernels (MFMA)
+// C[n x n] (ldc) = A^T B for A, B : rows x n (lda, ldb), summed over rows; when sym is set
+// only the lower-triangular tiles are computed and mirrored.  partial: device scratch of
+// splits * n * n doubles (split-K partial sums, reduced in a fixed order).
+hipError_t launch_gemm_tn(const double *A, int64_t lda, const double *B, int64_t ldb,
+                          int64_t rows, int64_t n, double *C, int64_t ldc, bool sym,
+                          double *partial, int splits, hipStream_t s);
+int gemm_tn_splits(int64_t rows, int64_t n);
+// C[rows x n] (ldc) = A[rows x n] (lda) * B[n x n] (ldb); when upper is set B is upper
+// triangular and its zero blocks are skipped.
+hipError_t launch_gemm_nn(const double *A, int64_t lda, const double *B, int64_t ldb,
+                          int64_t rows, int64_t n, double *C, int64_t ldc, bool upper,
+                          hipStream_t s);
+
+// ---- small dense FP64 factorisations (device)
+// In-place scaled Cholesky-QR core: given G (n x n, ld n) = Y^T Y, forms
+// D = diag(G)^{1/2}, Gs = D^-1 G D^-1, Gs = R^T R, and writes Rinv = D^-1 R^-1 (upper).
+// info (device int) is set non-zero on breakdown.
+hipError_t launch_chol_rinv(double *G, int64_t n, double *Rinv, double *scratch, int *info,
+                            hipStream_t s);
+size_t chol_rinv_scratch_doubles(int64_t n);
+
+hipError_t launch_symmetrize(double *A, int64_t n, int64_t lda, hipStream_t s);
+
+// symmetric eigensolver; work sized by syev_work_bytes
+size_t syev_work_bytes(int64_t n);
+hipError_t run_syev(int64_t n, const double *A, int64_t lda, double *lambda, double *Z,
+                    int64_t ldz, void *work, hipStream_t s, int *host_info);
+
+// ---- adjoint helper: dH[t] (+)= coef * Abar[rowblock(t)] * B[colblock(t)]^T on the pattern
+hipError_t launch_sddmm(const ttdft_bsr &H, const void *Abar, int64_t lda, const void *Bk,
+                        int64_t ldb, int64_t n_vec, double coef, void *dH, const uint64_t *mask,
+                        bool accumulate, ttdft_dtype xt, hipStream_t s);
+
+}  // namespace ttdft

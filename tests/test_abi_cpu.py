@@ -1,0 +1,172 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, rejects bad arguments before any device work, and the host
+BSR builder reproduces the CSR matrix exactly."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workload
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x10000  # never dereferenced: validation fails before any device access
+
+
+def declared_symbols():
+    syms = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", f)).read()
+            syms |= set(re.findall(r"^\S.*?\b(ttdft_\w+)\s*\(", txt, flags=re.M))
+    return syms
+
+
+def test_exports_every_declared_symbol(lib_built):
+    from paper_2110_15853_amd import _lib
+    lib = C.CDLL(lib_built)
+    syms = declared_symbols()
+    assert len(syms) >= 10
+    for s in sorted(syms):
+        assert hasattr(lib, s), s
+    assert syms <= set(_lib.SIGNATURES), sorted(syms - set(_lib.SIGNATURES))
+
+
+def _lib():
+    from paper_2110_15853_amd import _lib as L
+    return L
+
+
+def _fake_bsr(nbr=8, nt=64, dtype=0):
+    return _lib().Bsr(nbr, nt, FAKE, FAKE, FAKE, dtype)
+
+
+def _filter(**kw):
+    L = _lib()
+    args = dict(H=_fake_bsr(), X=FAKE, ldx=16, Y=FAKE * 1000, ldy=16, n=16, m=10, a=2.0,
+                b=12.5, a0=-3.0, dt=0, work=FAKE * 100000, wb=1 << 40, s=None)
+    args.update(kw)
+    H = args["H"]
+    return L.load().ttdft_cheb_filter(C.byref(H) if H is not None else None, args["X"], args["ldx"],
+                                      args["Y"], args["ldy"], args["n"], args["m"], args["a"],
+                                      args["b"], args["a0"], args["dt"], args["work"], args["wb"],
+                                      args["s"])
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(H=None), "TTDFT_ERR_NULL"),
+    (dict(X=None), "TTDFT_ERR_NULL"),
+    (dict(a0=2.0), "TTDFT_ERR_BOUNDS"),
+    (dict(b=2.0), "TTDFT_ERR_BOUNDS"),
+    (dict(a=float("nan")), "TTDFT_ERR_BOUNDS"),
+    (dict(b=float("inf")), "TTDFT_ERR_BOUNDS"),
+    (dict(m=0), "TTDFT_ERR_DEGREE"),
+    (dict(m=-3), "TTDFT_ERR_DEGREE"),
+    (dict(n=0), "TTDFT_ERR_SHAPE"),
+    (dict(ldx=8), "TTDFT_ERR_SHAPE"),
+    (dict(dt=7), "TTDFT_ERR_DTYPE"),
+    (dict(dt=1), "TTDFT_ERR_DTYPE"),          # F64 H with F32 X
+    (dict(H=_fake_bsr(dtype=2), dt=0), "TTDFT_ERR_DTYPE"),
+    (dict(H=_fake_bsr(nbr=0)), "TTDFT_ERR_SHAPE"),
+    (dict(Y=FAKE + 8), "TTDFT_ERR_ALIAS"),    # Y overlaps X
+    (dict(work=FAKE + 64), "TTDFT_ERR_ALIAS"),
+    (dict(wb=10), "TTDFT_ERR_WORKSPACE"),
+    (dict(work=None), "TTDFT_ERR_WORKSPACE"),
+])
+def test_filter_validation(lib_built, kw, status):
+    L = _lib()
+    st = _filter(**kw)
+    assert L.STATUS[st] == status, L.load().ttdft_last_error()
+    assert L.load().ttdft_last_error().decode() != ""
+
+
+def test_step_and_cast_validation(lib_built):
+    L = _lib()
+    lib = L.load()
+    H = _fake_bsr()
+    st = lib.ttdft_cheb_step(C.byref(H), FAKE, 16, None, 0, FAKE * 1000, 16, 16, 1.0, 0.0, 0.5, 0, None)
+    assert L.STATUS[st] == "TTDFT_ERR_NULL"            # beta != 0 needs Yprev
+    st = lib.ttdft_cheb_step(C.byref(H), FAKE, 16, None, 0, FAKE, 16, 16, 1.0, 0.0, 0.0, 0, None)
+    assert L.STATUS[st] == "TTDFT_ERR_ALIAS"           # Yout overlaps Yk
+    st = lib.ttdft_cheb_step(C.byref(H), FAKE, 16, None, 0, FAKE * 1000, 16, 16, float("nan"), 0.0, 0.0, 0, None)
+    assert L.STATUS[st] == "TTDFT_ERR_NONFINITE"
+    st = lib.ttdft_cast(FAKE, 0, 16, FAKE + 8, 1, 16, 4, 16, None)
+    assert L.STATUS[st] == "TTDFT_ERR_ALIAS"
+    st = lib.ttdft_cast(FAKE, 0, 8, FAKE * 1000, 1, 16, 4, 16, None)
+    assert L.STATUS[st] == "TTDFT_ERR_SHAPE"
+    st = lib.ttdft_gather_rows(FAKE, 16, 4, FAKE * 1000, 16, 4, 16, None, 0, None)
+    assert L.STATUS[st] == "TTDFT_ERR_NULL"
+    assert lib.ttdft_status_string(8).decode() == "Cholesky breakdown"
+
+
+def _bsr_host(r, h, dtype_code, seed=0):
+    L = _lib()
+    lib = L.load()
+    ip, ix, d, N = workload.lattice_hamiltonian(r, h, seed)
+    nbr, nt = C.c_int64(), C.c_int64()
+    P = lambda a: C.c_void_p(a.ctypes.data)
+    assert lib.ttdft_bsr_plan(r, P(ip), P(ix), C.byref(nbr), C.byref(nt)) == 0
+    nbr, nt = nbr.value, nt.value
+    tptr, tcol = np.empty(nbr + 1, np.int32), np.empty(nt, np.int32)
+    vals = np.empty(nt * 4096, {0: np.float64, 1: np.float32, 2: np.uint16}[dtype_code])
+    perm, slot, mask = np.empty(nbr * 64, np.int64), np.empty(len(d), np.int64), np.empty(nt * 64, np.uint64)
+    assert lib.ttdft_bsr_build(r, P(ip), P(ix), P(d), dtype_code, P(tptr), P(tcol), P(vals), P(perm),
+                               P(slot), P(mask)) == 0
+    return (ip, ix, d, N), (nbr, nt, tptr, tcol, vals, perm, slot, mask)
+
+
+@pytest.mark.parametrize("r,h", [(4, 1), (6, 2), (10, 3), (8, 4), (5, 3)])
+def test_bsr_builder_roundtrip(lib_built, r, h):
+    (ip, ix, d, N), (nbr, nt, tptr, tcol, vals, perm, slot, mask) = _bsr_host(r, h, 0)
+    nb = (r + 3) // 4
+    assert nbr == nb ** 3 and tptr[-1] == nt
+    Hd = oracle.csr_from_arrays(ip, ix, d, N).toarray()
+    dense = np.zeros((nbr * 64, nbr * 64))
+    for B in range(nbr):
+        assert np.all(np.diff(tcol[tptr[B]:tptr[B + 1]]) > 0)
+        for t in range(tptr[B], tptr[B + 1]):
+            dense[B * 64:(B + 1) * 64, tcol[t] * 64:(tcol[t] + 1) * 64] = vals[t * 4096:(t + 1) * 4096].reshape(64, 64)
+    real = perm >= 0
+    assert real.sum() == N and sorted(perm[real]) == list(range(N))
+    back = np.zeros((N, N))
+    back[np.ix_(perm[real], perm[real])] = dense[np.ix_(real, real)]
+    np.testing.assert_array_equal(back, Hd)            # bitwise
+    assert not dense[~real].any() and not dense[:, ~real].any()
+    np.testing.assert_array_equal(vals[slot], d)
+    # mask marks exactly the stored entries
+    bits = np.zeros(nt * 4096, bool)
+    bits[slot] = True
+    weights = (np.uint64(1) << np.arange(64, dtype=np.uint64))
+    words = (bits.reshape(nt * 64, 64).astype(np.uint64) * weights).sum(axis=1, dtype=np.uint64)
+    np.testing.assert_array_equal(words, mask)
+    # lattice blocking: every tile couples blocks at most one block apart per axis when h <= 4
+    for B in range(nbr):
+        bi, bj, bk = B // (nb * nb), (B // nb) % nb, B % nb
+        for t in range(tptr[B], tptr[B + 1]):
+            c = tcol[t]
+            ci, cj, ck = c // (nb * nb), (c // nb) % nb, c % nb
+            assert max(abs(ci - bi), abs(cj - bj), abs(ck - bk)) <= 1
+
+
+def test_bsr_builder_low_precision_rounding(lib_built):
+    import torch
+    (ip, ix, d, N), (_, _, _, _, v32, _, slot, _) = _bsr_host(5, 2, 1)
+    np.testing.assert_array_equal(v32[slot], d.astype(np.float32))
+    (ip, ix, d, N), (_, _, _, _, v16, _, slot, _) = _bsr_host(5, 2, 2)
+    ref = torch.from_numpy(d.astype(np.float32)).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    np.testing.assert_array_equal(v16[slot], ref)
+
+
+def test_bsr_builder_rejects_bad_csr(lib_built):
+    L = _lib()
+    lib = L.load()
+    ip = np.array([0, 2, 3, 4, 5, 6, 7, 8, 9], np.int64)      # r = 2, N = 8
+    ix = np.array([1, 0, 2, 3, 4, 5, 6, 7, 8], np.int32)       # row 0 unsorted; col 8 out of range
+    nbr, nt = C.c_int64(), C.c_int64()
+    P = lambda a: C.c_void_p(a.ctypes.data)
+    st = lib.ttdft_bsr_plan(2, P(ip), P(ix), C.byref(nbr), C.byref(nt))
+    assert L.STATUS[st] == "TTDFT_ERR_PATTERN"
+    st = lib.ttdft_bsr_plan(0, P(ip), P(ix), C.byref(nbr), C.byref(nt))
+    assert L.STATUS[st] == "TTDFT_ERR_SHAPE"
