@@ -56,6 +56,7 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=8)
+    ap.add_argument("--no-rr", action="store_true", help="time the filter alone")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -85,8 +86,15 @@ def main():
         Xb = P.cast(Xb, xdt)
     Y = torch.empty_like(Xb)
     work = torch.empty(Xb.numel() * Xb.element_size(), dtype=torch.uint8, device="cuda")
+    do_rr = not args.no_rr
+    if do_rr:
+        H64 = H if args.precision == "f64" else P.bsr_build(ip, ix, d, cfg.r, dtype=torch.float64,
+                                                             device="cuda")
+        rr_work = torch.empty(P.rayleigh_ritz_workspace(H64, cfg.n, Xb.dtype), dtype=torch.uint8,
+                              device="cuda")
     torch.cuda.synchronize()
     log("inputs resident on the GPU")
+    rr_out = {}
 
     def step(ev=None):
         if ev is not None:
@@ -94,13 +102,17 @@ def main():
         P.cheb_filter(H, Xb, cfg.m, cfg.a, cfg.b, cfg.a0, out=Y, work=work)
         if ev is not None:
             ev[1].record()
+        if do_rr:
+            rr_out["lam"], rr_out["psi"] = P.rayleigh_ritz(H64, Y, work=rr_work)
+            if ev is not None:
+                ev[2].record()
 
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup}")
 
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    events = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3))
               for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -108,8 +120,10 @@ def main():
         step(events[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    filt_ms = [a.elapsed_time(b) for a, b in events]
-    log(f"timed {args.steps} steps: wall {wall:.3f} s, filter ms {['%.1f' % v for v in filt_ms]}")
+    filt_ms = [ev[0].elapsed_time(ev[1]) for ev in events]
+    rr_ms = [ev[1].elapsed_time(ev[2]) for ev in events] if do_rr else []
+    log(f"timed {args.steps} steps: wall {wall:.3f} s, filter ms {['%.1f' % v for v in filt_ms]}, "
+        f"Rayleigh-Ritz ms {['%.1f' % v for v in rr_ms]}")
 
     nnz = len(d)
     n = cfg.n
@@ -138,8 +152,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg.name, "N": N, "rows_blocked": H.rows, "n_vec": n, "m": cfg.m,
                    "h": cfg.h, "nnz": nnz, "tiles": H.n_tiles, "fill": nnz / (H.n_tiles * 4096),
-                   "a": cfg.a, "b": cfg.b, "a0": cfg.a0, "step": "chebyshev filter"},
+                   "a": cfg.a, "b": cfg.b, "a0": cfg.a0,
+                   "step": "chebyshev filter + FP64 Rayleigh-Ritz" if do_rr else "chebyshev filter"},
         "filter_ms": round(filt_s * 1e3, 3),
+        "rayleigh_ritz_ms": round(float(np.mean(rr_ms)), 3) if do_rr else None,
         "hbm_gbs_algorithmic": round(alg_bytes_launch / launch_s / 1e9, 1),
         "issued_tflops": round(issued_flops_launch / launch_s / 1e12, 2),
         "issued_frac": round(issued_flops_launch / launch_s / 1e12 / peak, 4),

@@ -162,6 +162,84 @@ ttdft_status ttdft_gather_rows(const void *src, int64_t lds, int64_t rows_src, v
                                int64_t ldd, int64_t rows_dst, int64_t cols,
                                const int64_t *perm, ttdft_dtype dtype, void *stream);
 
+/* ---------------------------------------------------------------- steps 2-5: Rayleigh-Ritz */
+
+/* Bytes of workspace ttdft_cholqr2 needs for an n_rows x n_vec block. */
+size_t ttdft_cholqr2_workspace(int64_t n_rows, int64_t n_vec, ttdft_dtype y_dtype);
+
+/*
+ * Step 2 of Algorithm 1 (orthonormalisation of the filtered block), carried
+ * out as Cholesky-QR applied twice in FP64 with column scaling:
+ *   G = Y^T Y,  D = diag(G)^{1/2},  D^{-1} G D^{-1} = R^T R,  Q = Y D^{-1} R^{-1},
+ * then once more on Q.  Q^T Q = I and span(Q) = span(Y).
+ * Y: device n_rows x n_vec (F64, F32 or BF16; read in FP64).  Q: device FP64
+ * n_rows x n_vec; Q may be Y only when Y is F64 with ldq == ldy, otherwise
+ * they must not overlap.  Requires n_rows >= n_vec.  Synchronises the stream
+ * (a breakdown must be reported).
+ * Errors: NULL, SHAPE, DTYPE, WORKSPACE, ALIAS, NOT_POSDEF (a non-positive
+ * pivot: Y numerically rank-deficient in FP64), HIP.
+ */
+ttdft_status ttdft_cholqr2(const void *Y, int64_t ldy, ttdft_dtype y_dtype, int64_t n_rows,
+                           int64_t n_vec, double *Q, int64_t ldq, void *work,
+                           size_t work_bytes, void *stream);
+
+/* Bytes of workspace ttdft_project needs (H Q, plus split-K partial sums). */
+size_t ttdft_project_workspace(const ttdft_bsr *H, int64_t n_vec);
+
+/*
+ * Step 3 of Algorithm 1 (subspace projection, Sec. 4.3): A = Q^T (H Q),
+ * written symmetrised as (A + A^T)/2.  H must be FP64.  Q: device FP64
+ * 64*n_block_rows x n_vec (ldq).  A: device FP64 n_vec x n_vec (lda).  ASYNC.
+ * Errors: NULL, SHAPE, DTYPE, WORKSPACE, ALIAS, HIP.
+ */
+ttdft_status ttdft_project(const ttdft_bsr *H, const double *Q, int64_t ldq, int64_t n_vec,
+                           double *A, int64_t lda, void *work, size_t work_bytes,
+                           void *stream);
+
+/* Bytes of workspace ttdft_syev needs for order n. */
+size_t ttdft_syev_workspace(int64_t n);
+
+/*
+ * Step 4 of Algorithm 1 (dense eigensolve of the projected matrix):
+ * A Z = Z diag(lambda) for a symmetric n x n FP64 matrix A (device, lda; only
+ * read), lambda ascending (device [n]), Z orthonormal (device n x n, ldz;
+ * column j belongs to lambda[j]).  Householder tridiagonalisation, bisection,
+ * inverse iteration, re-orthonormalisation and back-transformation, all on the
+ * GPU.  Synchronises the stream.
+ * Errors: NULL, SHAPE, WORKSPACE, ALIAS, NO_CONVERGENCE (eigenvector block lost
+ * rank), NONFINITE (non-finite entries in A), HIP.
+ */
+ttdft_status ttdft_syev(int64_t n, const double *A, int64_t lda, double *lambda, double *Z,
+                        int64_t ldz, void *work, size_t work_bytes, void *stream);
+
+/*
+ * Step 5 of Algorithm 1 (rotation): Psi = X_F Q with X_F device FP64
+ * n_rows x n_vec (ldx), Q device FP64 n_vec x n_vec (ldq) and Psi device FP64
+ * n_rows x n_vec (ldpsi), Psi overlapping neither input.  ASYNC.
+ * Errors: NULL, SHAPE, ALIAS, HIP.
+ */
+ttdft_status ttdft_rotate(const double *XF, int64_t ldx, int64_t n_rows, int64_t n_vec,
+                          const double *Q, int64_t ldq, double *Psi, int64_t ldpsi,
+                          void *stream);
+
+/* Bytes of workspace ttdft_rayleigh_ritz needs. */
+size_t ttdft_rayleigh_ritz_workspace(const ttdft_bsr *H, int64_t n_vec, ttdft_dtype y_dtype);
+
+/*
+ * Steps 2-5 of Algorithm 1 on a filtered block Y (the output of step 1):
+ * X_F = Cholesky-QR2(Y); H_F = X_F^T H X_F; H_F Q = Q Lambda; Psi = X_F Q.
+ * H must be FP64: the projection stays in FP64 whatever precision the filter
+ * used.  Y: device 64*n_block_rows x n_vec of y_dtype.  lambda: device FP64
+ * [n_vec], ascending.  Psi: device FP64 64*n_block_rows x n_vec (ldpsi).
+ * Synchronises the stream.
+ * Errors: NULL, SHAPE, DTYPE, WORKSPACE, ALIAS, NOT_POSDEF, NO_CONVERGENCE,
+ * NONFINITE, HIP.
+ */
+ttdft_status ttdft_rayleigh_ritz(const ttdft_bsr *H, const void *Y, int64_t ldy,
+                                 ttdft_dtype y_dtype, int64_t n_vec, double *lambda,
+                                 double *Psi, int64_t ldpsi, void *work, size_t work_bytes,
+                                 void *stream);
+
 /* ---------------------------------------------------------------- diagnostics */
 
 const char *ttdft_status_string(ttdft_status s);

@@ -15,5 +15,12 @@ from .api import (  # noqa: F401
     from_blocked,
     to_blocked,
     DTYPE_CODES,
+    cholqr2,
+    gather_rows,
+    project,
+    rayleigh_ritz,
+    rayleigh_ritz_workspace,
+    rotate,
+    syev,
 )
 from ._lib import TtdftError, library_path  # noqa: F401

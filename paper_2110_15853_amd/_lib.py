@@ -46,6 +46,15 @@ SIGNATURES = {
                                  _SZ, _P]),
     "ttdft_cast": (_INT, [_P, _INT, _I64, _P, _INT, _I64, _I64, _I64, _P]),
     "ttdft_gather_rows": (_INT, [_P, _I64, _I64, _P, _I64, _I64, _I64, _P, _INT, _P]),
+    "ttdft_cholqr2_workspace": (_SZ, [_I64, _I64, _INT]),
+    "ttdft_cholqr2": (_INT, [_P, _I64, _INT, _I64, _I64, _P, _I64, _P, _SZ, _P]),
+    "ttdft_project_workspace": (_SZ, [_BSRP, _I64]),
+    "ttdft_project": (_INT, [_BSRP, _P, _I64, _I64, _P, _I64, _P, _SZ, _P]),
+    "ttdft_syev_workspace": (_SZ, [_I64]),
+    "ttdft_syev": (_INT, [_I64, _P, _I64, _P, _P, _I64, _P, _SZ, _P]),
+    "ttdft_rotate": (_INT, [_P, _I64, _I64, _I64, _P, _I64, _P, _I64, _P]),
+    "ttdft_rayleigh_ritz_workspace": (_SZ, [_BSRP, _I64, _INT]),
+    "ttdft_rayleigh_ritz": (_INT, [_BSRP, _P, _I64, _INT, _I64, _P, _P, _I64, _P, _SZ, _P]),
     "ttdft_status_string": (C.c_char_p, [_INT]),
     "ttdft_last_error": (C.c_char_p, []),
     "ttdft_version": (C.c_char_p, []),

@@ -159,3 +159,69 @@ def cheb_filter(H: BsrMatrix, X: torch.Tensor, m: int, a: float, b: float, a0: f
     _lib.call("ttdft_cheb_filter", C.byref(hs), _ptr(X), _ld(X), _ptr(out), _ld(out), n, m,
               a, b, a0, code, _ptr(work), work.numel() if work is not None else 0, _stream())
     return out
+
+
+def _work(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def cholqr2(Y: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:
+    """ttdft_cholqr2: FP64 Cholesky-QR twice (step 2 of Algorithm 1)."""
+    rows, n = Y.shape
+    if out is None:
+        out = torch.empty((rows, n), dtype=torch.float64, device=Y.device)
+    need = _lib.load().ttdft_cholqr2_workspace(rows, n, _code(Y))
+    w = _work(need, Y.device)
+    _lib.call("ttdft_cholqr2", _ptr(Y), _ld(Y), _code(Y), rows, n, _ptr(out), _ld(out), _ptr(w),
+              w.numel(), _stream())
+    return out
+
+
+def project(H: BsrMatrix, Q: torch.Tensor) -> torch.Tensor:
+    """ttdft_project: (Q^T H Q + (Q^T H Q)^T)/2 in FP64 (step 3 of Algorithm 1)."""
+    hs = H.c_struct()
+    n = Q.shape[1]
+    A = torch.empty((n, n), dtype=torch.float64, device=Q.device)
+    w = _work(_lib.load().ttdft_project_workspace(C.byref(hs), n), Q.device)
+    _lib.call("ttdft_project", C.byref(hs), _ptr(Q), _ld(Q), n, _ptr(A), _ld(A), _ptr(w),
+              w.numel(), _stream())
+    return A
+
+
+def syev(A: torch.Tensor):
+    """ttdft_syev: eigenvalues (ascending) and eigenvectors of a symmetric FP64 matrix."""
+    n = A.shape[0]
+    lam = torch.empty(n, dtype=torch.float64, device=A.device)
+    Z = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    w = _work(_lib.load().ttdft_syev_workspace(n), A.device)
+    _lib.call("ttdft_syev", n, _ptr(A), _ld(A), _ptr(lam), _ptr(Z), _ld(Z), _ptr(w), w.numel(),
+              _stream())
+    return lam, Z
+
+
+def rotate(XF: torch.Tensor, Q: torch.Tensor) -> torch.Tensor:
+    """ttdft_rotate: Psi = X_F Q (step 5 of Algorithm 1)."""
+    rows, n = XF.shape
+    Psi = torch.empty((rows, n), dtype=torch.float64, device=XF.device)
+    _lib.call("ttdft_rotate", _ptr(XF), _ld(XF), rows, n, _ptr(Q), _ld(Q), _ptr(Psi), _ld(Psi),
+              _stream())
+    return Psi
+
+
+def rayleigh_ritz(H: BsrMatrix, Y: torch.Tensor, work: torch.Tensor = None):
+    """ttdft_rayleigh_ritz: steps 2-5 of Algorithm 1; returns (lambda, Psi)."""
+    hs = H.c_struct()
+    n = Y.shape[1]
+    lam = torch.empty(n, dtype=torch.float64, device=Y.device)
+    Psi = torch.empty((H.rows, n), dtype=torch.float64, device=Y.device)
+    need = _lib.load().ttdft_rayleigh_ritz_workspace(C.byref(hs), n, _code(Y))
+    if work is None or work.numel() < need:
+        work = _work(need, Y.device)
+    _lib.call("ttdft_rayleigh_ritz", C.byref(hs), _ptr(Y), _ld(Y), _code(Y), n, _ptr(lam),
+              _ptr(Psi), _ld(Psi), _ptr(work), work.numel(), _stream())
+    return lam, Psi
+
+
+def rayleigh_ritz_workspace(H: BsrMatrix, n: int, dtype=torch.float64) -> int:
+    hs = H.c_struct()
+    return int(_lib.load().ttdft_rayleigh_ritz_workspace(C.byref(hs), n, DTYPE_CODES[dtype]))

@@ -149,6 +149,11 @@ void block_pattern(const Lattice &L, const int64_t *rowptr, const int32_t *col,
 
 }  // namespace
 
+namespace ttdft {
+ttdft_status api_fail(ttdft_status s, const char *msg) { return fail(s, "%s", msg); }
+ttdft_status api_ok() { return ok(); }
+}  // namespace ttdft
+
 extern "C" {
 
 const char *ttdft_version(void) { return "ttdft-gfx950 0.1"; }

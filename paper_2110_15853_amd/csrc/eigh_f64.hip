@@ -1,0 +1,390 @@
+// Dense symmetric eigensolver in FP64 for the projected matrix H_F of step 4 of
+// Algorithm 1 (Sec. 3.4):  H_F Z = Z diag(lambda), lambda ascending.
+//
+//  1. Householder tridiagonalisation H_F = Q T Q^T, one reflector per column
+//     (reflector, symmetric product, correction vector, rank-2 update);
+//  2. eigenvalues of T by bisection on Sturm counts, one eigenvalue per thread;
+//  3. eigenvectors of T by inverse iteration (tridiagonal LU with partial
+//     pivoting), one eigenvector per thread, from pseudo-random starts;
+//  4. Cholesky-QR twice on the eigenvector block (matrix-core GEMMs), which
+//     restores orthogonality lost between close eigenvalues; mixing inside such
+//     a group changes residuals only in proportion to the gap;
+//  5. back-transformation Z = Q Z_T by the reflectors in reverse order.
+// Every stage is parallel across the matrix or across eigenpairs except the
+// sequence of n-2 reflectors.
+#include "ttdft_internal.h"
+
+namespace ttdft {
+namespace {
+
+constexpr double EPS = 2.220446049250313e-16;
+constexpr double SAFMIN = 2.2250738585072014e-308;
+
+template <int NT> __device__ inline double block_sum(double v, double *red) {
+  // wave reduction then across waves through LDS
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
+    red[NT / 64] = s;
+  }
+  __syncthreads();
+  s = red[NT / 64];
+  __syncthreads();
+  return s;
+}
+
+__global__ void copy_matrix_kernel(const double *A, int64_t lda, double *B, int64_t ldb, int64_t n) {
+  const int64_t total = n * n;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / n, j = e % n;
+    B[i * ldb + j] = A[i * lda + j];
+  }
+}
+
+// Householder reflector for row k (x = A[k][k+1:n]); v (v0 = 1) overwrites
+// A[k][k+1:n]; d[k] = A[k][k], e[k] = beta, tau[k].
+__global__ __launch_bounds__(1024) void house_kernel(double *A, int64_t n, int64_t k, double *tau,
+                                                     double *d, double *e, int *nonfinite) {
+  __shared__ double red[1024 / 64 + 1];
+  double *x = A + k * n + k + 1;
+  const int64_t m = n - k - 1;
+  double s = 0.0;
+  for (int64_t i = 1 + threadIdx.x; i < m; i += 1024) s += x[i] * x[i];
+  const double xn2 = block_sum<1024>(s, red);
+  const double alpha = x[0];
+  double beta, t, scale;
+  if (xn2 == 0.0) {
+    t = 0.0;
+    beta = alpha;
+    scale = 0.0;
+  } else {
+    beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+    t = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  __syncthreads();
+  for (int64_t i = 1 + threadIdx.x; i < m; i += 1024) x[i] *= scale;
+  if (threadIdx.x == 0) {
+    if (!isfinite(beta) || !isfinite(t)) atomicExch(nonfinite, 1);
+    x[0] = 1.0;
+    tau[k] = t;
+    d[k] = A[k * n + k];
+    e[k] = beta;
+  }
+}
+
+// p_i = tau * sum_j A[i][j] v_j over the trailing block (one wave per row);
+// pv_i = p_i * v_i for the correction scalar.
+__global__ __launch_bounds__(256) void symv_kernel(const double *A, int64_t n, int64_t k,
+                                                   const double *tau, double *p, double *pv) {
+  const int64_t m = n - k - 1;
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= m) return;
+  const double *v = A + k * n + k + 1;
+  const double *row = A + (k + 1 + r) * n + k + 1;
+  double s = 0.0;
+  for (int64_t j = lane; j < m; j += 64) s += row[j] * v[j];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (lane == 0) {
+    const double pi = tau[k] * s;
+    p[r] = pi;
+    pv[r] = pi * v[r];
+  }
+}
+
+// w = p - (tau/2)(p.v) v
+__global__ __launch_bounds__(1024) void wvec_kernel(const double *A, int64_t n, int64_t k,
+                                                    const double *tau, const double *p,
+                                                    const double *pv, double *w) {
+  __shared__ double red[1024 / 64 + 1];
+  const int64_t m = n - k - 1;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < m; i += 1024) s += pv[i];
+  const double K = 0.5 * tau[k] * block_sum<1024>(s, red);
+  const double *v = A + k * n + k + 1;
+  for (int64_t i = threadIdx.x; i < m; i += 1024) w[i] = p[i] - K * v[i];
+}
+
+// A22 -= v w^T + w v^T
+__global__ __launch_bounds__(256) void rank2_kernel(double *A, int64_t n, int64_t k, const double *w) {
+  const int64_t m = n - k - 1;
+  const double *v = A + k * n + k + 1;
+  const int64_t total = m * m;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / m, j = e % m;
+    double *a = A + (k + 1 + i) * n + k + 1 + j;
+    *a = *a - (v[i] * w[j] + w[i] * v[j]);
+  }
+}
+
+__global__ void tail_kernel(const double *A, int64_t n, double *d, double *e) {
+  if (threadIdx.x != 0) return;
+  if (n >= 2) {
+    d[n - 2] = A[(n - 2) * n + n - 2];
+    e[n - 2] = A[(n - 1) * n + n - 2];
+  }
+  d[n - 1] = A[(n - 1) * n + n - 1];
+}
+
+// number of eigenvalues of T smaller than x (Sturm count of the LDL^T pivots)
+__device__ inline int sturm_count(const double *d, const double *e, int64_t n, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += q < 0.0;
+  for (int64_t i = 1; i < n; ++i) {
+    q = (d[i] - x) - e[i - 1] * e[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// lambda[j] = j-th smallest eigenvalue of T, one thread per j
+__global__ __launch_bounds__(256) void bisect_kernel(const double *d, const double *e, int64_t n,
+                                                     double *lambda, double *tnorm_out) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  double lo = d[0], hi = d[0], emax2 = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+    lo = fmin(lo, d[i] - r);
+    hi = fmax(hi, d[i] + r);
+    if (i + 1 < n) emax2 = fmax(emax2, e[i] * e[i]);
+  }
+  const double tnorm = fmax(fabs(lo), fabs(hi));
+  const double pivmin = SAFMIN * fmax(1.0, emax2);
+  lo -= 2.0 * EPS * tnorm * n + pivmin;
+  hi += 2.0 * EPS * tnorm * n + pivmin;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (hi - lo <= 2.0 * EPS * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin || mid == lo || mid == hi) break;
+    if (sturm_count(d, e, n, mid, pivmin) > j) hi = mid;
+    else lo = mid;
+  }
+  lambda[j] = 0.5 * (lo + hi);
+  if (j == 0) *tnorm_out = tnorm;
+}
+
+__device__ inline double start_value(int64_t i, int64_t j) {
+  uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull ^ ((uint64_t)j + 0x632BE59BD9B4E019ull) * 0xBF58476D1CE4E5B9ull;
+  h ^= h >> 31;
+  h *= 0x94D049BB133111EBull;
+  h ^= h >> 29;
+  return (double)(h >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
+// Eigenvector of T for lambda[j] by three steps of inverse iteration; thread j
+// owns column j of Zt (row-major n x n) and columns j of the factor arrays
+// (element i of thread j at [i*n + j], so a wave's accesses are contiguous).
+__global__ __launch_bounds__(256) void inverse_iteration_kernel(
+    const double *d, const double *e, int64_t n, const double *lambda, const double *tnorm,
+    double *Zt, double *dg, double *du, double *du2, double *dl, double *swp) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  const double lam = lambda[j];
+  const double tiny = EPS * fmax(*tnorm, SAFMIN * 1e16);
+#define AT(arr, i) arr[(int64_t)(i) * n + j]
+  // LU with partial pivoting of T - lam I
+  for (int64_t i = 0; i < n; ++i) {
+    AT(dg, i) = d[i] - lam;
+    if (i + 1 < n) { AT(du, i) = e[i]; AT(dl, i) = e[i]; }
+    if (i + 2 < n) AT(du2, i) = 0.0;
+  }
+  for (int64_t i = 0; i + 1 < n; ++i) {
+    const double gi = AT(dg, i), li = AT(dl, i);
+    if (fabs(gi) >= fabs(li)) {
+      const double g = gi != 0.0 ? gi : tiny;
+      AT(dg, i) = g;
+      const double f = li / g;
+      AT(dl, i) = f;
+      AT(dg, i + 1) = AT(dg, i + 1) - f * AT(du, i);
+      AT(swp, i) = 0.0;
+    } else {
+      const double f = gi / li;
+      AT(dg, i) = li;
+      AT(dl, i) = f;
+      const double tmp = AT(du, i);
+      AT(du, i) = AT(dg, i + 1);
+      AT(dg, i + 1) = tmp - f * AT(dg, i + 1);
+      if (i + 2 < n) {
+        AT(du2, i) = AT(du, i + 1);
+        AT(du, i + 1) = -f * AT(du, i + 1);
+      }
+      AT(swp, i) = 1.0;
+    }
+  }
+  if (AT(dg, n - 1) == 0.0) AT(dg, n - 1) = tiny;
+  double nrm = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double s = start_value(i, j);
+    AT(Zt, i) = s;
+    nrm += s * s;
+  }
+  for (int it = 0; it < 3; ++it) {
+    const double inv = 1.0 / sqrt(nrm);
+    // forward: apply row swaps and multipliers (L y = P b)
+    for (int64_t i = 0; i < n; ++i) AT(Zt, i) *= inv;
+    for (int64_t i = 0; i + 1 < n; ++i) {
+      double bi = AT(Zt, i), bn = AT(Zt, i + 1);
+      if (AT(swp, i) != 0.0) { const double t = bi; bi = bn; bn = t; AT(Zt, i) = bi; }
+      AT(Zt, i + 1) = bn - AT(dl, i) * bi;
+    }
+    // backward: U x = y
+    nrm = 0.0;
+    for (int64_t i = n - 1; i >= 0; --i) {
+      double s = AT(Zt, i);
+      if (i + 1 < n) s -= AT(du, i) * AT(Zt, i + 1);
+      if (i + 2 < n) s -= AT(du2, i) * AT(Zt, i + 2);
+      const double xi = s / AT(dg, i);
+      AT(Zt, i) = xi;
+      nrm += xi * xi;
+    }
+    if (!(nrm > 0.0) || !isfinite(nrm)) {  // fall back to a fresh start
+      nrm = 0.0;
+      for (int64_t i = 0; i < n; ++i) {
+        const double s = start_value(i, j + (int64_t)(it + 1) * n);
+        AT(Zt, i) = s;
+        nrm += s * s;
+      }
+    }
+  }
+  const double inv = 1.0 / sqrt(nrm);
+  for (int64_t i = 0; i < n; ++i) AT(Zt, i) *= inv;
+#undef AT
+}
+
+// Back-transformation by one reflector: Z[k+1:, :] -= tau v (v^T Z[k+1:, :]).
+// Pass 1: partial[y][c] = sum over rows 64y .. 64y+63 of v_i Z[i][c].
+__global__ __launch_bounds__(256) void backtr_partial_kernel(const double *A, int64_t n, int64_t k,
+                                                             const double *Z, int64_t ldz,
+                                                             double *partial) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= n) return;
+  const int64_t m = n - k - 1, r0 = (int64_t)blockIdx.y * 64, r1 = min(m, r0 + 64);
+  const double *v = A + k * n + k + 1;
+  double s = 0.0;
+  for (int64_t i = r0; i < r1; ++i) s += v[i] * Z[(k + 1 + i) * ldz + c];
+  partial[(int64_t)blockIdx.y * n + c] = s;
+}
+
+// Pass 2: w_c = sum_y partial[y][c] (fixed order), then the rows of chunk y.
+__global__ __launch_bounds__(256) void backtr_update_kernel(const double *A, int64_t n, int64_t k,
+                                                            const double *tau, double *Z,
+                                                            int64_t ldz, const double *partial) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= n) return;
+  const int64_t m = n - k - 1, ny = (m + 63) / 64;
+  double w = 0.0;
+  for (int64_t y = 0; y < ny; ++y) w += partial[y * n + c];
+  const double tw = tau[k] * w;
+  const double *v = A + k * n + k + 1;
+  const int64_t r0 = (int64_t)blockIdx.y * 64, r1 = min(m, r0 + 64);
+  for (int64_t i = r0; i < r1; ++i) Z[(k + 1 + i) * ldz + c] -= v[i] * tw;
+}
+
+__global__ void clear_ints_kernel(int *p, int count) {
+  if (threadIdx.x < count) p[threadIdx.x] = 0;
+}
+
+inline unsigned grid_for(int64_t work) {
+  const int64_t g = (work + 255) / 256;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+}
+
+struct SyevLayout {
+  int64_t n, np, splits;
+  size_t a, dg, du, du2, dl, swp, zt, z2, g, m, chol, partial, vec, info, total;
+};
+
+SyevLayout syev_layout(int64_t n) {
+  SyevLayout L;
+  L.n = n;
+  L.np = (n + 63) / 64 * 64;
+  L.splits = gemm_tn_splits(n, n);
+  size_t off = 0;
+  auto take = [&](size_t doubles) { size_t o = off; off += (doubles * 8 + 255) / 256 * 256; return o; };
+  const size_t nn = (size_t)n * n, npnp = (size_t)L.np * L.np;
+  L.a = take(nn);
+  L.dg = take(nn); L.du = take(nn); L.du2 = take(nn); L.dl = take(nn); L.swp = take(nn);
+  L.zt = take(nn);
+  L.z2 = take(nn);
+  L.g = take(npnp);
+  L.m = take(npnp);
+  L.chol = take(chol_rinv_scratch_doubles(n));
+  L.partial = take((size_t)L.splits * nn);
+  L.vec = take(8 * (size_t)n + 8);
+  L.info = take(4);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+hipError_t launch_clear_ints(int *p, int count, hipStream_t s) {
+  hipLaunchKernelGGL(clear_ints_kernel, dim3(1), dim3(64), 0, s, p, count);
+  return hipGetLastError();
+}
+
+size_t syev_work_bytes(int64_t n) { return n < 1 ? 0 : syev_layout(n).total; }
+
+hipError_t run_syev(int64_t n, const double *Ain, int64_t lda, double *lambda, double *Z,
+                    int64_t ldz, void *work, hipStream_t s, int *host_info) {
+  const SyevLayout L = syev_layout(n);
+  char *w = (char *)work;
+  double *A = (double *)(w + L.a), *dg = (double *)(w + L.dg), *du = (double *)(w + L.du);
+  double *du2 = (double *)(w + L.du2), *dl = (double *)(w + L.dl), *swp = (double *)(w + L.swp);
+  double *Zt = (double *)(w + L.zt), *Z2 = (double *)(w + L.z2), *G = (double *)(w + L.g);
+  double *M = (double *)(w + L.m), *chol = (double *)(w + L.chol);
+  double *partial = (double *)(w + L.partial), *vec = (double *)(w + L.vec);
+  double *tau = vec, *d = vec + n, *e = vec + 2 * n, *p = vec + 3 * n, *pv = vec + 4 * n;
+  double *wv = vec + 5 * n, *tnorm = vec + 8 * n;
+  int *info = (int *)(w + L.info);
+  hipError_t err;
+  hipLaunchKernelGGL(clear_ints_kernel, dim3(1), dim3(64), 0, s, info, 4);
+  hipLaunchKernelGGL(copy_matrix_kernel, dim3(grid_for(n * n)), dim3(256), 0, s, Ain, lda, A, n, n);
+  // 1. tridiagonalisation
+  for (int64_t k = 0; k + 2 < n; ++k) {
+    const int64_t m = n - k - 1;
+    hipLaunchKernelGGL(house_kernel, dim3(1), dim3(1024), 0, s, A, n, k, tau, d, e, info + 1);
+    hipLaunchKernelGGL(symv_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, A, n, k, tau, p, pv);
+    hipLaunchKernelGGL(wvec_kernel, dim3(1), dim3(1024), 0, s, A, n, k, tau, p, pv, wv);
+    hipLaunchKernelGGL(rank2_kernel, dim3(grid_for(m * m)), dim3(256), 0, s, A, n, k, wv);
+  }
+  hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(64), 0, s, A, n, d, e);
+  // 2. eigenvalues
+  hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, e, n,
+                     lambda, tnorm);
+  // 3. eigenvectors of T
+  hipLaunchKernelGGL(inverse_iteration_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     d, e, n, lambda, tnorm, Zt, dg, du, du2, dl, swp);
+  // 4. Cholesky-QR twice: Zt <- Zt M
+  for (int pass = 0; pass < 2; ++pass) {
+    double *src = pass == 0 ? Zt : Z2, *dst = pass == 0 ? Z2 : Zt;
+    if ((err = launch_gemm_tn_ex(src, n, src, n, n, n, G, L.np, true, false, partial,
+                                 (int)L.splits, s)) != hipSuccess) return err;
+    if ((err = launch_chol_rinv(G, n, M, chol, info, s)) != hipSuccess) return err;
+    if ((err = launch_gemm_nn_ex(src, n, M, L.np, n, n, n, 1.0, dst, n, true, s)) != hipSuccess) return err;
+  }
+  // 5. back-transformation Z = H_0 ... H_{n-3} Zt
+  hipLaunchKernelGGL(copy_matrix_kernel, dim3(grid_for(n * n)), dim3(256), 0, s, Zt, n, Z, ldz, n);
+  for (int64_t k = n - 3; k >= 0; --k) {
+    const dim3 g((unsigned)((n + 255) / 256), (unsigned)((n - k - 1 + 63) / 64));
+    hipLaunchKernelGGL(backtr_partial_kernel, g, dim3(256), 0, s, A, n, k, Z, ldz, du);
+    hipLaunchKernelGGL(backtr_update_kernel, g, dim3(256), 0, s, A, n, k, tau, Z, ldz, du);
+  }
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  if ((err = hipStreamSynchronize(s)) != hipSuccess) return err;
+  int h[2] = {0, 0};
+  if ((err = hipMemcpy(h, info, sizeof h, hipMemcpyDeviceToHost)) != hipSuccess) return err;
+  host_info[0] = h[0];
+  host_info[1] = h[1];
+  return hipSuccess;
+}
+
+}  // namespace ttdft

@@ -1,0 +1,290 @@
+// Host side of steps 2-5 of Algorithm 1 (Sec. 3.4), all in FP64 on the GPU:
+// Cholesky-QR twice with column scaling, the projection X_F^T (H X_F) with the
+// fused BSR kernel and a matrix-core GEMM, the dense eigensolve and the
+// rotation Psi = X_F Q.  Validation runs before any device work.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+
+#include "ttdft_internal.h"
+
+using namespace ttdft;
+
+namespace ttdft {
+// defined in api.cpp
+ttdft_status api_fail(ttdft_status s, const char *msg);
+ttdft_status api_ok();
+}
+
+namespace {
+
+thread_local char g_msg[256];
+
+ttdft_status failf(ttdft_status s, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_msg, sizeof g_msg, fmt, ap);
+  va_end(ap);
+  return api_fail(s, g_msg);
+}
+
+ttdft_status hip_fail(hipError_t e, const char *what) {
+  return failf(TTDFT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool valid_dtype(int t) { return t == TTDFT_F64 || t == TTDFT_F32 || t == TTDFT_BF16; }
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+  if (!a || !b || !na || !nb) return false;
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+size_t block_bytes(int64_t rows, int64_t ld, int64_t cols, size_t elt) {
+  return rows <= 0 || cols <= 0 ? 0 : (size_t)((rows - 1) * ld + cols) * elt;
+}
+
+// workspace of the Cholesky-QR core: W (rows x n, ld n), G and M (np x np),
+// factorisation scratch, split-K partials, info flags
+struct QrLayout {
+  int64_t np;
+  int splits;
+  size_t w, g, m, chol, partial, info, total;
+};
+QrLayout qr_layout(int64_t rows, int64_t n) {
+  QrLayout L;
+  L.np = (n + 63) / 64 * 64;
+  L.splits = gemm_tn_splits(rows, n);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  L.w = take((size_t)rows * n * 8);
+  L.g = take((size_t)L.np * L.np * 8);
+  L.m = take((size_t)L.np * L.np * 8);
+  L.chol = take(chol_rinv_scratch_doubles(n) * 8);
+  L.partial = take((size_t)L.splits * n * n * 8);
+  L.info = take(16);
+  L.total = off;
+  return L;
+}
+
+// Y (any dtype) -> Q (FP64) = Cholesky-QR applied twice.  Enqueues only.
+hipError_t cholqr2_enqueue(const void *Y, int64_t ldy, ttdft_dtype ydt, int64_t rows, int64_t n,
+                           double *Q, int64_t ldq, char *work, const QrLayout &L, hipStream_t s) {
+  double *W = (double *)(work + L.w), *G = (double *)(work + L.g), *M = (double *)(work + L.m);
+  double *chol = (double *)(work + L.chol), *partial = (double *)(work + L.partial);
+  int *info = (int *)(work + L.info);
+  hipError_t e;
+  if ((e = launch_clear_ints(info, 4, s)) != hipSuccess) return e;
+  const double *src = (const double *)Y;
+  int64_t lds = ldy;
+  if (ydt != TTDFT_F64) {  // precision cast: the orthonormalisation is FP64
+    if ((e = launch_cast(Y, ydt, ldy, Q, TTDFT_F64, ldq, rows, n, s)) != hipSuccess) return e;
+    src = Q;
+    lds = ldq;
+  }
+  if ((e = launch_gemm_tn(src, lds, src, lds, rows, n, G, L.np, true, partial, L.splits, s))) return e;
+  if ((e = launch_chol_rinv(G, n, M, chol, info, s)) != hipSuccess) return e;
+  if ((e = launch_gemm_nn_ex(src, lds, M, L.np, rows, n, n, 1.0, W, n, true, s))) return e;
+  if ((e = launch_gemm_tn(W, n, W, n, rows, n, G, L.np, true, partial, L.splits, s))) return e;
+  if ((e = launch_chol_rinv(G, n, M, chol, info, s)) != hipSuccess) return e;
+  return launch_gemm_nn_ex(W, n, M, L.np, rows, n, n, 1.0, Q, ldq, true, s);
+}
+
+ttdft_status check_h64(const ttdft_bsr *H) {
+  if (!H) return failf(TTDFT_ERR_NULL, "H is NULL");
+  if (H->dtype != TTDFT_F64) return failf(TTDFT_ERR_DTYPE, "the projection needs an FP64 H");
+  if (H->n_block_rows < 1 || H->n_tiles < 0) return failf(TTDFT_ERR_SHAPE, "bad H shape");
+  if (!H->tile_rowptr || (H->n_tiles > 0 && (!H->tile_col || !H->vals)))
+    return failf(TTDFT_ERR_NULL, "H arrays are NULL");
+  return TTDFT_OK;
+}
+
+struct ProjLayout {
+  int splits;
+  size_t hq, partial, total;
+};
+ProjLayout proj_layout(int64_t rows, int64_t n) {
+  ProjLayout L;
+  L.splits = gemm_tn_splits(rows, n);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  L.hq = take((size_t)rows * n * 8);
+  L.partial = take((size_t)L.splits * n * n * 8);
+  L.total = off;
+  return L;
+}
+
+hipError_t project_enqueue(const ttdft_bsr &H, const double *Q, int64_t ldq, int64_t n, double *A,
+                           int64_t lda, char *work, const ProjLayout &L, hipStream_t s) {
+  const int64_t rows = H.n_block_rows * 64;
+  double *HQ = (double *)(work + L.hq), *partial = (double *)(work + L.partial);
+  hipError_t e = launch_cheb_step(H, Q, ldq, nullptr, 0, HQ, n, n, 1.0, 0.0, 0.0, TTDFT_F64, s);
+  if (e != hipSuccess) return e;
+  return launch_gemm_tn_ex(Q, ldq, HQ, n, rows, n, A, lda, false, true, partial, L.splits, s);
+}
+
+struct RrLayout {
+  QrLayout qr;
+  ProjLayout pj;
+  size_t xf, qr_off, pj_off, hf, zq, syev, total;
+};
+RrLayout rr_layout(int64_t rows, int64_t n) {
+  RrLayout L;
+  L.qr = qr_layout(rows, n);
+  L.pj = proj_layout(rows, n);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  L.xf = take((size_t)rows * n * 8);
+  // the Cholesky-QR scratch and the projection scratch are used one after the other
+  const size_t shared = std::max(L.qr.total, L.pj.total);
+  L.qr_off = take(shared);
+  L.pj_off = L.qr_off;
+  L.hf = take((size_t)n * n * 8);
+  L.zq = take((size_t)n * n * 8);
+  L.syev = take(syev_work_bytes(n));
+  L.total = off;
+  return L;
+}
+
+ttdft_status finish_qr(char *work, const QrLayout &L, hipStream_t s) {
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "cholqr2");
+  int info[2] = {0, 0};
+  e = hipMemcpy(info, work + L.info, sizeof info, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "cholqr2 info");
+  if (info[0]) return failf(TTDFT_ERR_NOT_POSDEF, "Cholesky breakdown at column %d: block rank-deficient in FP64", info[0]);
+  return TTDFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ttdft_cholqr2_workspace(int64_t n_rows, int64_t n_vec, ttdft_dtype y_dtype) {
+  if (n_rows < 1 || n_vec < 1 || !valid_dtype(y_dtype)) return 0;
+  return qr_layout(n_rows, n_vec).total;
+}
+
+ttdft_status ttdft_cholqr2(const void *Y, int64_t ldy, ttdft_dtype y_dtype, int64_t n_rows,
+                           int64_t n_vec, double *Q, int64_t ldq, void *work, size_t work_bytes,
+                           void *stream) {
+  if (!valid_dtype(y_dtype)) return failf(TTDFT_ERR_DTYPE, "unknown dtype");
+  if (!Y || !Q) return failf(TTDFT_ERR_NULL, "Y or Q is NULL");
+  if (n_vec < 1 || n_rows < n_vec || ldy < n_vec || ldq < n_vec)
+    return failf(TTDFT_ERR_SHAPE, "need n_rows >= n_vec >= 1 and ld >= n_vec");
+  const QrLayout L = qr_layout(n_rows, n_vec);
+  if (!work || work_bytes < L.total) return failf(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", L.total);
+  const size_t yb = block_bytes(n_rows, ldy, n_vec, y_dtype == TTDFT_F64 ? 8 : y_dtype == TTDFT_F32 ? 4 : 2);
+  const size_t qb = block_bytes(n_rows, ldq, n_vec, 8);
+  if (overlap(Y, yb, Q, qb) && !(y_dtype == TTDFT_F64 && (const void *)Y == (const void *)Q && ldy == ldq))
+    return failf(TTDFT_ERR_ALIAS, "Q overlaps Y");
+  if (overlap(work, L.total, Q, qb) || overlap(work, L.total, Y, yb))
+    return failf(TTDFT_ERR_ALIAS, "workspace overlaps Y or Q");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = cholqr2_enqueue(Y, ldy, y_dtype, n_rows, n_vec, Q, ldq, (char *)work, L, s);
+  if (e != hipSuccess) return hip_fail(e, "cholqr2 launch");
+  ttdft_status st = finish_qr((char *)work, L, s);
+  return st == TTDFT_OK ? api_ok() : st;
+}
+
+size_t ttdft_project_workspace(const ttdft_bsr *H, int64_t n_vec) {
+  if (!H || H->n_block_rows < 1 || n_vec < 1) return 0;
+  return proj_layout(H->n_block_rows * 64, n_vec).total;
+}
+
+ttdft_status ttdft_project(const ttdft_bsr *H, const double *Q, int64_t ldq, int64_t n_vec,
+                           double *A, int64_t lda, void *work, size_t work_bytes, void *stream) {
+  ttdft_status st = check_h64(H);
+  if (st != TTDFT_OK) return st;
+  if (!Q || !A) return failf(TTDFT_ERR_NULL, "Q or A is NULL");
+  if (n_vec < 1 || ldq < n_vec || lda < n_vec) return failf(TTDFT_ERR_SHAPE, "bad shape");
+  const int64_t rows = H->n_block_rows * 64;
+  const ProjLayout L = proj_layout(rows, n_vec);
+  if (!work || work_bytes < L.total) return failf(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", L.total);
+  const size_t qb = block_bytes(rows, ldq, n_vec, 8), ab = block_bytes(n_vec, lda, n_vec, 8);
+  if (overlap(Q, qb, A, ab) || overlap(work, L.total, A, ab) || overlap(work, L.total, Q, qb))
+    return failf(TTDFT_ERR_ALIAS, "buffers overlap");
+  hipError_t e = project_enqueue(*H, Q, ldq, n_vec, A, lda, (char *)work, L, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "project launch");
+  return api_ok();
+}
+
+size_t ttdft_syev_workspace(int64_t n) { return n < 1 ? 0 : syev_work_bytes(n); }
+
+ttdft_status ttdft_syev(int64_t n, const double *A, int64_t lda, double *lambda, double *Z,
+                        int64_t ldz, void *work, size_t work_bytes, void *stream) {
+  if (!A || !lambda || !Z) return failf(TTDFT_ERR_NULL, "A, lambda or Z is NULL");
+  if (n < 1 || lda < n || ldz < n) return failf(TTDFT_ERR_SHAPE, "bad shape");
+  const size_t need = syev_work_bytes(n);
+  if (!work || work_bytes < need) return failf(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", need);
+  const size_t ab = block_bytes(n, lda, n, 8), zb = block_bytes(n, ldz, n, 8);
+  if (overlap(A, ab, Z, zb) || overlap(lambda, (size_t)n * 8, Z, zb) || overlap(lambda, (size_t)n * 8, A, ab) ||
+      overlap(work, need, Z, zb) || overlap(work, need, A, ab) || overlap(work, need, lambda, (size_t)n * 8))
+    return failf(TTDFT_ERR_ALIAS, "buffers overlap");
+  int info[2] = {0, 0};
+  hipError_t e = run_syev(n, A, lda, lambda, Z, ldz, work, (hipStream_t)stream, info);
+  if (e != hipSuccess) return hip_fail(e, "syev");
+  if (info[1]) return failf(TTDFT_ERR_NONFINITE, "non-finite value in the tridiagonal reduction");
+  if (info[0]) return failf(TTDFT_ERR_NO_CONVERGENCE, "eigenvector block lost rank (column %d)", info[0]);
+  return api_ok();
+}
+
+ttdft_status ttdft_rotate(const double *XF, int64_t ldx, int64_t n_rows, int64_t n_vec,
+                          const double *Q, int64_t ldq, double *Psi, int64_t ldpsi, void *stream) {
+  if (!XF || !Q || !Psi) return failf(TTDFT_ERR_NULL, "XF, Q or Psi is NULL");
+  if (n_rows < 1 || n_vec < 1 || ldx < n_vec || ldq < n_vec || ldpsi < n_vec)
+    return failf(TTDFT_ERR_SHAPE, "bad shape");
+  const size_t xb = block_bytes(n_rows, ldx, n_vec, 8), qb = block_bytes(n_vec, ldq, n_vec, 8),
+               pb = block_bytes(n_rows, ldpsi, n_vec, 8);
+  if (overlap(Psi, pb, XF, xb) || overlap(Psi, pb, Q, qb)) return failf(TTDFT_ERR_ALIAS, "Psi overlaps an input");
+  hipError_t e = launch_gemm_nn_ex(XF, ldx, Q, ldq, n_rows, n_vec, n_vec, 1.0, Psi, ldpsi, false,
+                                   (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "rotate launch");
+  return api_ok();
+}
+
+size_t ttdft_rayleigh_ritz_workspace(const ttdft_bsr *H, int64_t n_vec, ttdft_dtype y_dtype) {
+  if (!H || H->n_block_rows < 1 || n_vec < 1 || !valid_dtype(y_dtype)) return 0;
+  return rr_layout(H->n_block_rows * 64, n_vec).total;
+}
+
+ttdft_status ttdft_rayleigh_ritz(const ttdft_bsr *H, const void *Y, int64_t ldy, ttdft_dtype y_dtype,
+                                 int64_t n_vec, double *lambda, double *Psi, int64_t ldpsi,
+                                 void *work, size_t work_bytes, void *stream) {
+  ttdft_status st = check_h64(H);
+  if (st != TTDFT_OK) return st;
+  if (!valid_dtype(y_dtype)) return failf(TTDFT_ERR_DTYPE, "unknown dtype");
+  if (!Y || !lambda || !Psi) return failf(TTDFT_ERR_NULL, "Y, lambda or Psi is NULL");
+  const int64_t rows = H->n_block_rows * 64;
+  if (n_vec < 1 || n_vec > rows || ldy < n_vec || ldpsi < n_vec) return failf(TTDFT_ERR_SHAPE, "bad shape");
+  const RrLayout L = rr_layout(rows, n_vec);
+  if (!work || work_bytes < L.total) return failf(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", L.total);
+  const size_t elt = y_dtype == TTDFT_F64 ? 8 : y_dtype == TTDFT_F32 ? 4 : 2;
+  const size_t yb = block_bytes(rows, ldy, n_vec, elt), pb = block_bytes(rows, ldpsi, n_vec, 8);
+  if (overlap(Psi, pb, Y, yb) || overlap(work, L.total, Psi, pb) || overlap(work, L.total, Y, yb) ||
+      overlap(lambda, (size_t)n_vec * 8, Psi, pb) || overlap(lambda, (size_t)n_vec * 8, work, L.total))
+    return failf(TTDFT_ERR_ALIAS, "buffers overlap");
+  char *w = (char *)work;
+  hipStream_t s = (hipStream_t)stream;
+  double *XF = (double *)(w + L.xf), *Hf = (double *)(w + L.hf), *Zq = (double *)(w + L.zq);
+  hipError_t e = cholqr2_enqueue(Y, ldy, y_dtype, rows, n_vec, XF, n_vec, w + L.qr_off, L.qr, s);
+  if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: cholqr2");
+  st = finish_qr(w + L.qr_off, L.qr, s);
+  if (st != TTDFT_OK) return st;
+  e = project_enqueue(*H, XF, n_vec, n_vec, Hf, n_vec, w + L.pj_off, L.pj, s);
+  if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: projection");
+  int info[2] = {0, 0};
+  e = run_syev(n_vec, Hf, n_vec, lambda, Zq, n_vec, w + L.syev, s, info);
+  if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: eigensolve");
+  if (info[1]) return failf(TTDFT_ERR_NONFINITE, "non-finite value in the projected matrix");
+  if (info[0]) return failf(TTDFT_ERR_NO_CONVERGENCE, "eigenvector block lost rank");
+  e = launch_gemm_nn_ex(XF, n_vec, Zq, n_vec, rows, n_vec, n_vec, 1.0, Psi, ldpsi, false, s);
+  if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: rotation");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz");
+  return api_ok();
+}
+
+}  // extern "C"

@@ -34,12 +34,21 @@ hipError_t launch_gather_rows(const void *src, int64_t lds, void *dst, int64_t l
 hipError_t launch_gemm_tn(const double *A, int64_t lda, const double *B, int64_t ldb,
                           int64_t rows, int64_t n, double *C, int64_t ldc, bool sym,
                           double *partial, int splits, hipStream_t s);
+// as launch_gemm_tn; symmetrize writes (C + C^T)/2
+hipError_t launch_gemm_tn_ex(const double *A, int64_t lda, const double *B, int64_t ldb,
+                             int64_t rows, int64_t n, double *C, int64_t ldc, bool sym,
+                             bool symmetrize, double *partial, int splits, hipStream_t s);
 int gemm_tn_splits(int64_t rows, int64_t n);
 // C[rows x n] (ldc) = A[rows x n] (lda) * B[n x n] (ldb); when upper is set B is upper
 // triangular and its zero blocks are skipped.
 hipError_t launch_gemm_nn(const double *A, int64_t lda, const double *B, int64_t ldb,
                           int64_t rows, int64_t n, double *C, int64_t ldc, bool upper,
                           hipStream_t s);
+// C[rows x N] = alpha * A[rows x K] B[K x N]
+hipError_t launch_gemm_nn_ex(const double *A, int64_t lda, const double *B, int64_t ldb,
+                             int64_t rows, int64_t K, int64_t N, double alpha, double *C,
+                             int64_t ldc, bool upper, hipStream_t s);
+hipError_t launch_clear_ints(int *p, int count, hipStream_t s);
 
 // ---- small dense FP64 factorisations (device)
 // In-place scaled Cholesky-QR core: given G (n x n, ld n) = Y^T Y, forms

@@ -1,0 +1,130 @@
+"""GPU parity of steps 2-5 of Algorithm 1 (Cholesky-QR, projection, dense
+eigensolve, rotation) against the FP64 oracle and LAPACK, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import workload
+from gpu_common import A, A0, B, make_case, normwise, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _cuda(x):
+    torch, _ = require_gpu()
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.mark.parametrize("rows,n,cond_exp", [(3000, 100, 4), (1000, 37, 2), (700, 130, 6),
+                                             (64, 64, 1), (5000, 1, 0), (2049, 257, 3)])
+def test_cholqr2_matches_householder(rows, n, cond_exp):
+    print(f"cholqr2 rows={rows} n={n}", flush=True)
+    torch, P = require_gpu()
+    rng = np.random.default_rng(rows + n)
+    Y = rng.standard_normal((rows, n)) * np.logspace(0, cond_exp, n)[None, :]
+    Q = P.cholqr2(_cuda(Y)).cpu().numpy()
+    assert np.max(np.abs(Q.T @ Q - np.eye(n))) <= 1e-13
+    # thin QR with positive diagonal R is unique, so Q equals the oracle's
+    ref = oracle.orth(Y)
+    assert np.max(np.abs(Q - ref)) <= 1e-13 * 10 ** cond_exp * max(1, n) ** 0.5
+
+
+def test_cholqr2_low_precision_input_and_in_place():
+    torch, P = require_gpu()
+    rng = np.random.default_rng(7)
+    Y = rng.standard_normal((2000, 90))
+    Y32 = _cuda(Y).float()
+    Q = P.cholqr2(Y32).cpu().numpy()
+    ref = oracle.orth(Y32.double().cpu().numpy())     # the FP32 values, exactly
+    assert np.max(np.abs(Q - ref)) <= 1e-12
+    Yd = _cuda(Y)
+    P.cholqr2(Yd, out=Yd)                              # Q written over an FP64 Y
+    assert np.max(np.abs(Yd.cpu().numpy() - oracle.orth(Y))) <= 1e-12
+
+
+def test_cholqr2_reports_breakdown():
+    torch, P = require_gpu()
+    rng = np.random.default_rng(8)
+    Y = rng.standard_normal((500, 20))
+    Y[:, 7] = Y[:, 3]                                  # rank-deficient
+    with pytest.raises(P.TtdftError) as ei:
+        P.cholqr2(_cuda(Y))
+    assert ei.value.name == "TTDFT_ERR_NOT_POSDEF"
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 37, 200, 513])
+def test_syev_random_symmetric(n):
+    print(f"syev n={n}", flush=True)
+    torch, P = require_gpu()
+    rng = np.random.default_rng(n)
+    M = rng.standard_normal((n, n))
+    S = (M + M.T) / 2
+    lam, Z = P.syev(_cuda(S))
+    lam, Z = lam.cpu().numpy(), Z.cpu().numpy()
+    ref = np.linalg.eigvalsh(S)
+    nrm = np.abs(ref).max()
+    assert np.max(np.abs(lam - ref)) <= 1e-13 * nrm * max(1, n) ** 0.5
+    assert np.max(np.abs(Z.T @ Z - np.eye(n))) <= 1e-13
+    assert np.max(np.abs(S @ Z - Z * lam)) <= 1e-12 * nrm
+
+
+def test_syev_closed_form_and_degenerate_spectra():
+    torch, P = require_gpu()
+    n = 300
+    T = 2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)     # known spectrum
+    lam, Z = P.syev(_cuda(T))
+    k = np.arange(1, n + 1)
+    np.testing.assert_allclose(lam.cpu().numpy(), np.sort(2 - 2 * np.cos(k * np.pi / (n + 1))), atol=1e-13)
+    # repeated eigenvalues: orthogonal conjugation of a diagonal with clusters
+    rng = np.random.default_rng(3)
+    Qr, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    d = np.repeat([-3.0, 0.5, 0.5000000001, 7.0], n // 4)
+    S = (Qr * d) @ Qr.T
+    S = (S + S.T) / 2
+    lam, Z = P.syev(_cuda(S))
+    lam, Z = lam.cpu().numpy(), Z.cpu().numpy()
+    assert np.max(np.abs(lam - np.sort(d))) <= 1e-13 * 7 * n ** 0.5
+    assert np.max(np.abs(Z.T @ Z - np.eye(n))) <= 1e-13
+    assert np.max(np.abs(S @ Z - Z * lam)) <= 1e-12 * 7
+    lam, Z = P.syev(_cuda(np.eye(5) * 2.5))                  # identity: any orthonormal basis
+    np.testing.assert_allclose(lam.cpu().numpy(), 2.5, atol=1e-15)
+    assert np.max(np.abs(Z.cpu().numpy().T @ Z.cpu().numpy() - np.eye(5))) <= 1e-14
+
+
+def test_rotate_and_project():
+    torch, P = require_gpu()
+    Hc, Hb, X = make_case(8, 3, 40, seed=5)
+    Q = oracle.orth(X)
+    Qb = P.to_blocked(_cuda(Q), Hb)
+    Ad = P.project(Hb, Qb).cpu().numpy()
+    ref = Q.T @ (Hc @ Q)
+    ref = (ref + ref.T) / 2
+    assert normwise(Ad, ref) <= 1e-13
+    assert np.array_equal(Ad, Ad.T)
+    rng = np.random.default_rng(2)
+    Zq = rng.standard_normal((40, 40))
+    Psi = P.from_blocked(P.rotate(Qb, _cuda(Zq)), Hb).cpu().numpy()
+    assert normwise(Psi, Q @ Zq) <= 1e-14
+
+
+@pytest.mark.parametrize("r,h,n,m", [(20, 3, 64, 10), (10, 3, 16, 16), (12, 2, 150, 8)])
+def test_rayleigh_ritz_matches_oracle(r, h, n, m):
+    print(f"rayleigh_ritz r={r} h={h} n={n} m={m}", flush=True)
+    torch, P = require_gpu()
+    Hc, Hb, X = make_case(r, h, n)
+    Xb = P.to_blocked(_cuda(X), Hb)
+    Yb = P.cheb_filter(Hb, Xb, m, A, B, A0)
+    lam, Psib = P.rayleigh_ritz(Hb, Yb)
+    lam, Psi = lam.cpu().numpy(), P.from_blocked(Psib, Hb).cpu().numpy()
+    Yref = oracle.cheb_filter(Hc, X, m, A, B, A0)
+    lref, Pref = oracle.rayleigh_ritz(Hc, Yref)
+    hn = np.abs(lref).max()
+    assert np.max(np.abs(lam - lref)) <= 1e-10
+    assert np.max(np.abs(Psi.T @ Psi - np.eye(n))) <= 1e-12
+    assert np.max(np.abs(Psi.T @ (Hc @ Psi) - np.diag(lam))) <= 1e-12 * hn
+    # Ritz vectors agree up to sign where the Ritz value is separated from its neighbours
+    gaps = np.minimum(np.diff(lref, prepend=-np.inf), np.diff(lref, append=np.inf))
+    sep = gaps > 1e-3
+    ov = np.abs(np.sum(Psi * Pref, axis=0))
+    assert np.all(np.abs(ov[sep] - 1) <= 1e-8)
+    assert not Psib.cpu().numpy()[(Hb.perm < 0).cpu().numpy()].any()
