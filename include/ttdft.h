@@ -240,6 +240,43 @@ ttdft_status ttdft_rayleigh_ritz(const ttdft_bsr *H, const void *Y, int64_t ldy,
                                  double *Psi, int64_t ldpsi, void *work, size_t work_bytes,
                                  void *stream);
 
+/* ---------------------------------------------------------------- adjoint of step 1 */
+
+/*
+ * Bytes of workspace ttdft_cheb_filter_backward needs: one block for the
+ * reverse sweep plus the stored forward iterates.  ckpt_every = 0 (or 1, 2)
+ * stores every iterate Y_1 .. Y_{m-1}; ckpt_every = s >= 3 stores the pairs
+ * (Y_{js}, Y_{js+1}) and recomputes the s-2 iterates between them.
+ */
+size_t ttdft_cheb_filter_backward_workspace(const ttdft_bsr *H, int64_t n_vec, int32_t m,
+                                            int32_t ckpt_every, ttdft_dtype x_dtype);
+
+/*
+ * Adjoint of ttdft_cheb_filter (step 1 of Algorithm 1, Sec. 3.4) for a loss L
+ * with dL/dY = dY.  With Y_0 = X and Y_{k+1} = alpha_k (H - cI) Y_k - beta_k
+ * Y_{k-1} the reverse sweep is Ybar_m = dY,
+ *   Ybar_k = alpha_k (H - cI) Ybar_{k+1} - beta_{k+1} Ybar_{k+2}  (beta_m = 0),
+ * and
+ *   dX = Ybar_0  (= p(H) dY, H symmetric),
+ *   dH[t][i][j] = sum_k alpha_k <Ybar_{k+1}[row i], Y_k[col j]>  for each stored
+ *   entry (i, j) of tile t: the derivative with respect to that entry with all
+ *   entries independent (the derivative along a symmetric perturbation of the
+ *   pair (i,j), (j,i) is the sum of the two).  Entries whose mask bit is clear
+ *   are written as 0.
+ * X, dY: device 64*n_block_rows x n_vec of x_dtype (ldx, lddy).  dX: same shape
+ * and dtype (lddx), overlapping neither X, dY nor work.  dH_vals: device
+ * [n_tiles][64][64], FP64 when x_dtype is F64 and FP32 otherwise.  mask: device
+ * [n_tiles*64] from ttdft_bsr_build, or NULL (every tile entry written).  The
+ * result does not depend on ckpt_every (bitwise).  ASYNC.
+ * Errors: NULL, SHAPE, DTYPE, BOUNDS, DEGREE, ALIAS, WORKSPACE, HIP.
+ */
+ttdft_status ttdft_cheb_filter_backward(const ttdft_bsr *H, const void *X, int64_t ldx,
+                                        const void *dY, int64_t lddy, int64_t n_vec, int32_t m,
+                                        double a, double b, double a0, ttdft_dtype x_dtype,
+                                        int32_t ckpt_every, void *dX, int64_t lddx,
+                                        void *dH_vals, const uint64_t *mask, void *work,
+                                        size_t work_bytes, void *stream);
+
 /* ---------------------------------------------------------------- diagnostics */
 
 const char *ttdft_status_string(ttdft_status s);

@@ -15,6 +15,9 @@ from .api import (  # noqa: F401
     from_blocked,
     to_blocked,
     DTYPE_CODES,
+    ChebFilter,
+    cheb_filter_autograd,
+    cheb_filter_backward,
     cholqr2,
     gather_rows,
     project,

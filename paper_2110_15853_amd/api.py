@@ -225,3 +225,47 @@ def rayleigh_ritz(H: BsrMatrix, Y: torch.Tensor, work: torch.Tensor = None):
 def rayleigh_ritz_workspace(H: BsrMatrix, n: int, dtype=torch.float64) -> int:
     hs = H.c_struct()
     return int(_lib.load().ttdft_rayleigh_ritz_workspace(C.byref(hs), n, DTYPE_CODES[dtype]))
+
+
+def cheb_filter_backward(H: BsrMatrix, X: torch.Tensor, dY: torch.Tensor, m: int, a: float,
+                         b: float, a0: float, ckpt_every: int = 0, use_mask: bool = True):
+    """ttdft_cheb_filter_backward: returns (dX, dH_vals) for dL/dY = dY."""
+    hs = H.c_struct()
+    n = X.shape[1]
+    code = _code(X)
+    dX = torch.empty_like(X)
+    dH = torch.empty((H.n_tiles, 64, 64), dtype=torch.float64 if code == F64 else torch.float32,
+                     device=X.device)
+    need = _lib.load().ttdft_cheb_filter_backward_workspace(C.byref(hs), n, m, ckpt_every, code)
+    w = _work(need, X.device)
+    _lib.call("ttdft_cheb_filter_backward", C.byref(hs), _ptr(X), _ld(X), _ptr(dY), _ld(dY), n, m,
+              a, b, a0, code, ckpt_every, _ptr(dX), _ld(dX), _ptr(dH),
+              _ptr(H.mask) if use_mask else C.c_void_p(0), _ptr(w), w.numel(), _stream())
+    return dX, dH
+
+
+class ChebFilter(torch.autograd.Function):
+    """Differentiable Chebyshev filter: forward ttdft_cheb_filter, backward
+    ttdft_cheb_filter_backward.  Inputs (vals, X) are differentiable; vals must
+    be the tensor held by H (its tile layout)."""
+
+    @staticmethod
+    def forward(ctx, vals, X, H, m, a, b, a0, ckpt_every):
+        if vals.data_ptr() != H.vals.data_ptr():
+            raise ValueError("vals must be H.vals")
+        ctx.H, ctx.m, ctx.a, ctx.b, ctx.a0, ctx.ckpt = H, m, a, b, a0, ckpt_every
+        ctx.save_for_backward(X)
+        return cheb_filter(H, X, m, a, b, a0)
+
+    @staticmethod
+    def backward(ctx, dY):
+        (X,) = ctx.saved_tensors
+        dX, dH = cheb_filter_backward(ctx.H, X, dY.contiguous(), ctx.m, ctx.a, ctx.b, ctx.a0,
+                                      ctx.ckpt)
+        return dH.to(ctx.H.vals.dtype), dX, None, None, None, None, None, None
+
+
+def cheb_filter_autograd(H: BsrMatrix, X: torch.Tensor, m: int, a: float, b: float, a0: float,
+                         ckpt_every: int = 0) -> torch.Tensor:
+    """Chebyshev filter that records the adjoint for torch.autograd."""
+    return ChebFilter.apply(H.vals, X, H, m, a, b, a0, ckpt_every)

@@ -152,6 +152,25 @@ void block_pattern(const Lattice &L, const int64_t *rowptr, const int32_t *col,
 namespace ttdft {
 ttdft_status api_fail(ttdft_status s, const char *msg) { return fail(s, "%s", msg); }
 ttdft_status api_ok() { return ok(); }
+
+// Algorithm 1: e = (b - a)/2, c = (b + a)/2, sigma_1 = e/(a0 - c), gamma = 2/sigma_1;
+// the first step uses alpha = sigma_1/e and no previous block; step i >= 2 uses
+// sigma_i = 1/(gamma - sigma_{i-1}), alpha = 2 sigma_i/e, beta = sigma_{i-1} sigma_i.
+void cheb_coefficients(int m, double a, double b, double a0, double *c, double *alpha,
+                       double *beta) {
+  const double e = 0.5 * (b - a);
+  *c = 0.5 * (b + a);
+  double sigma = e / (a0 - *c);
+  const double gamma = 2.0 / sigma;
+  alpha[0] = sigma / e;
+  beta[0] = 0.0;
+  for (int k = 1; k < m; ++k) {
+    const double sigma2 = 1.0 / (gamma - sigma);
+    alpha[k] = 2.0 * sigma2 / e;
+    beta[k] = sigma * sigma2;
+    sigma = sigma2;
+  }
+}
 }  // namespace ttdft
 
 extern "C" {
@@ -293,25 +312,22 @@ ttdft_status ttdft_cheb_filter(const ttdft_bsr *H, const void *X, int64_t ldx, v
   if (overlap(sw, sy) || overlap(sw, sx)) return fail(TTDFT_ERR_ALIAS, "workspace overlaps X or Y");
 
   // coefficient schedule of Algorithm 1 (Sec. 3.4), FP64 on the host
-  const double e = 0.5 * (b - a), c = 0.5 * (b + a);
-  double sigma = e / (a0 - c);
-  const double sigma1 = sigma, gamma = 2.0 / sigma1;
+  std::vector<double> alpha(m), beta(m);
+  double c;
+  cheb_coefficients(m, a, b, a0, &c, alpha.data(), beta.data());
   // Y_k for k >= 1 lives in Y when k has the parity of m, else in work, so the
   // last iterate lands in Y and Y_{k+1} overwrites Y_{k-1} in place.
   auto buf = [&](int k) -> void * { return (k % 2 == m % 2) ? Y : work; };
   auto ld_of = [&](int k) -> int64_t { return (k % 2 == m % 2) ? ldy : n_vec; };
   hipStream_t s = (hipStream_t)stream;
-  hipError_t err = launch_cheb_step(*H, X, ldx, nullptr, 0, buf(1), ld_of(1), n_vec,
-                                    sigma1 / e, c, 0.0, x_dtype, s);
-  if (err != hipSuccess) return hip_status(err, "cheb_filter step 1");
-  for (int k = 2; k <= m; ++k) {
-    const double sigma2 = 1.0 / (gamma - sigma);
-    const void *prev = (k == 2) ? X : buf(k - 2);
-    const int64_t ldp = (k == 2) ? ldx : ld_of(k - 2);
-    err = launch_cheb_step(*H, buf(k - 1), ld_of(k - 1), prev, ldp, buf(k), ld_of(k), n_vec,
-                           2.0 * sigma2 / e, c, sigma * sigma2, x_dtype, s);
+  for (int k = 0; k < m; ++k) {
+    const void *cur = k == 0 ? X : buf(k);
+    const int64_t ldc = k == 0 ? ldx : ld_of(k);
+    const void *prev = k == 0 ? nullptr : (k == 1 ? X : buf(k - 1));
+    const int64_t ldp = k == 0 ? 0 : (k == 1 ? ldx : ld_of(k - 1));
+    hipError_t err = launch_cheb_step(*H, cur, ldc, prev, ldp, buf(k + 1), ld_of(k + 1), n_vec,
+                                      alpha[k], c, beta[k], x_dtype, s);
     if (err != hipSuccess) return hip_status(err, "cheb_filter step");
-    sigma = sigma2;
   }
   return ok();
 }

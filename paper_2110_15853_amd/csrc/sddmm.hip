@@ -1,0 +1,127 @@
+// Sampled dense-dense product on the tile pattern of H, for the gradient of the
+// Chebyshev filter with respect to the stored entries of H:
+//     dH[t][i][j] (+)= coef * sum_c Abar[64*B + i][c] * Yk[64*B' + j][c]
+// for every stored tile t = (B, B'), entries outside the true pattern (mask bit
+// clear) written as 0.  One work-group owns one tile and sweeps the vector
+// dimension in 32-wide panels, both operands staged transposed in LDS
+// ([vector][row]) so every matrix-core operand read is 16 consecutive values.
+// FP64 inputs use the f64 16x16x4 op; FP32 and BF16 inputs accumulate in FP32
+// on the f32 16x16x4 op.  Each tile is written by one work-group in a fixed
+// order, so accumulation over the degree steps is deterministic.
+#include "ttdft_internal.h"
+
+namespace ttdft {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int BK = 32, THREADS = 256;
+
+template <typename TC> struct Op;
+template <> struct Op<double> {
+  using acc_t = v4d;
+  static __device__ inline acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lane, int t) { return (lane >> 4) + 4 * t; }
+};
+template <> struct Op<float> {
+  using acc_t = v4f;
+  static __device__ inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lane, int t) { return 4 * (lane >> 4) + t; }
+};
+
+// iterate value in the arithmetic type TC (exact: TC is at least as wide as TX)
+template <typename TC, typename TX> __device__ inline TC widen(TX v) { return (TC)v; }
+template <> __device__ inline float widen<float, __bf16>(__bf16 v) { return (float)v; }
+
+// TX: storage type of the iterates; TC: arithmetic / output type
+template <typename TX, typename TC>
+__global__ __launch_bounds__(THREADS) void sddmm_kernel(
+    const int32_t *__restrict__ rowptr, const int32_t *__restrict__ tcol, int64_t n_block_rows,
+    const TX *__restrict__ Abar, int64_t lda, const TX *__restrict__ Yk, int64_t ldb,
+    int64_t n_vec, TC coef, TC *__restrict__ dH, const uint64_t *__restrict__ mask,
+    int accumulate) {
+  using O = Op<TC>;
+  __shared__ TC sA[BK][64 + 1];
+  __shared__ TC sB[BK][64 + 1];
+  const int64_t t = blockIdx.x;
+  // block row of tile t: the last B with rowptr[B] <= t (binary search)
+  int64_t lo = 0, hi = n_block_rows;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) / 2;
+    if (rowptr[mid] <= t) lo = mid; else hi = mid;
+  }
+  const int64_t B = lo, Bc = tcol[t];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const TX *Ar = Abar + B * 64 * lda;
+  const TX *Br = Yk + Bc * 64 * ldb;
+
+  typename O::acc_t acc[4];
+  for (int j = 0; j < 4; ++j) acc[j] = typename O::acc_t{0, 0, 0, 0};
+
+  for (int64_t c0 = 0; c0 < n_vec; c0 += BK) {
+#pragma unroll
+    for (int q = 0; q < BK * 64 / THREADS; ++q) {
+      const int idx = tid + THREADS * q;
+      const int r = idx / BK, kk = idx % BK;     // consecutive threads walk the vector index
+      const int64_t c = c0 + kk;
+      const bool in = c < n_vec;
+      sA[kk][r] = in ? widen<TC, TX>(Ar[(int64_t)r * lda + c]) : TC(0);
+      sB[kk][r] = in ? widen<TC, TX>(Br[(int64_t)r * ldb + c]) : TC(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kq = 0; kq < BK; kq += 4) {
+      const TC a = sA[kq + (lane >> 4)][16 * w + (lane & 15)];
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) {
+        const TC b = sB[kq + (lane >> 4)][16 * jb + (lane & 15)];
+        acc[jb] = O::mma(a, b, acc[jb]);
+      }
+    }
+    __syncthreads();
+  }
+
+  TC *out = dH + t * kTileElems;
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) {
+    const int j = 16 * jb + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * w + O::row(lane, q);
+      const bool on = mask ? ((mask[t * 64 + i] >> j) & 1ull) != 0 : true;
+      TC v = coef * acc[jb][q];
+      if (accumulate) v += out[i * 64 + j];
+      out[i * 64 + j] = on ? v : TC(0);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_sddmm(const ttdft_bsr &H, const void *Abar, int64_t lda, const void *Bk,
+                        int64_t ldb, int64_t n_vec, double coef, void *dH, const uint64_t *mask,
+                        bool accumulate, ttdft_dtype xt, hipStream_t s) {
+  if (H.n_tiles == 0) return hipSuccess;
+  const dim3 grid((unsigned)H.n_tiles), block(THREADS);
+  const int acc = accumulate ? 1 : 0;
+  if (xt == TTDFT_F64)
+    hipLaunchKernelGGL((sddmm_kernel<double, double>), grid, block, 0, s, H.tile_rowptr, H.tile_col,
+                       H.n_block_rows, (const double *)Abar, lda, (const double *)Bk, ldb, n_vec,
+                       coef, (double *)dH, mask, acc);
+  else if (xt == TTDFT_F32)
+    hipLaunchKernelGGL((sddmm_kernel<float, float>), grid, block, 0, s, H.tile_rowptr, H.tile_col,
+                       H.n_block_rows, (const float *)Abar, lda, (const float *)Bk, ldb, n_vec,
+                       (float)coef, (float *)dH, mask, acc);
+  else
+    hipLaunchKernelGGL((sddmm_kernel<__bf16, float>), grid, block, 0, s, H.tile_rowptr, H.tile_col,
+                       H.n_block_rows, (const __bf16 *)Abar, lda, (const __bf16 *)Bk, ldb, n_vec,
+                       (float)coef, (float *)dH, mask, acc);
+  return hipGetLastError();
+}
+
+}  // namespace ttdft

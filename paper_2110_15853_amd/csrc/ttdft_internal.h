@@ -15,6 +15,12 @@ inline size_t dtype_size(ttdft_dtype t) {
 constexpr int kTile = 64;                    // rows per lattice block (4x4x4)
 constexpr int64_t kTileElems = 64 * 64;
 
+// ---- coefficient schedule of the scaled recurrence (Algorithm 1, Sec. 3.4):
+// step k (k = 0 .. m-1) forms Y_{k+1} = alpha[k] (H - cI) Y_k - beta[k] Y_{k-1},
+// beta[0] = 0.  alpha and beta hold m entries.
+void cheb_coefficients(int m, double a, double b, double a0, double *c, double *alpha,
+                       double *beta);
+
 // ---- fused BSR SpMM + Chebyshev recurrence epilogue (one degree step)
 hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, const void *Yp,
                             int64_t ldp, void *Yo, int64_t ldo, int64_t n_vec, double alpha,

@@ -170,3 +170,54 @@ def test_bsr_builder_rejects_bad_csr(lib_built):
     assert L.STATUS[st] == "TTDFT_ERR_PATTERN"
     st = lib.ttdft_bsr_plan(0, P(ip), P(ix), C.byref(nbr), C.byref(nt))
     assert L.STATUS[st] == "TTDFT_ERR_SHAPE"
+
+
+def test_rayleigh_ritz_and_backward_validation(lib_built):
+    L = _lib()
+    lib = L.load()
+    H64, H32 = _fake_bsr(), _fake_bsr(dtype=1)
+    big = 1 << 40
+    # Rayleigh-Ritz needs an FP64 H
+    st = lib.ttdft_rayleigh_ritz(C.byref(H32), FAKE, 16, 1, 16, FAKE * 10, FAKE * 1000, 16, FAKE * 100000, big, None)
+    assert L.STATUS[st] == "TTDFT_ERR_DTYPE"
+    st = lib.ttdft_rayleigh_ritz(C.byref(H64), FAKE, 16, 0, 16, None, FAKE * 1000, 16, FAKE * 100000, big, None)
+    assert L.STATUS[st] == "TTDFT_ERR_NULL"
+    st = lib.ttdft_rayleigh_ritz(C.byref(H64), FAKE, 16, 0, 16, FAKE * 10, FAKE * 1000, 16, FAKE * 100000, 8, None)
+    assert L.STATUS[st] == "TTDFT_ERR_WORKSPACE"
+    st = lib.ttdft_cholqr2(FAKE, 16, 0, 8, 16, FAKE * 1000, 16, FAKE * 100000, big, None)
+    assert L.STATUS[st] == "TTDFT_ERR_SHAPE"                      # fewer rows than vectors
+    st = lib.ttdft_cholqr2(FAKE, 16, 1, 100, 16, FAKE, 16, FAKE * 100000, big, None)
+    assert L.STATUS[st] == "TTDFT_ERR_ALIAS"                      # F32 Y cannot alias Q
+    st = lib.ttdft_syev(10, FAKE, 10, FAKE * 1000, FAKE + 8, 10, FAKE * 100000, big, None)
+    assert L.STATUS[st] == "TTDFT_ERR_ALIAS"
+    st = lib.ttdft_syev(0, FAKE, 10, FAKE * 1000, FAKE * 3000, 10, FAKE * 100000, big, None)
+    assert L.STATUS[st] == "TTDFT_ERR_SHAPE"
+    st = lib.ttdft_rotate(FAKE, 16, 100, 16, FAKE * 1000, 16, FAKE + 16, 16, None)
+    assert L.STATUS[st] == "TTDFT_ERR_ALIAS"
+    st = lib.ttdft_project(C.byref(H32), FAKE, 16, 16, FAKE * 1000, 16, FAKE * 100000, big, None)
+    assert L.STATUS[st] == "TTDFT_ERR_DTYPE"
+    # backward
+    bw = lambda **kw: lib.ttdft_cheb_filter_backward(
+        C.byref(kw.get("H", H64)), FAKE, 16, FAKE * 1000, 16, 16, kw.get("m", 10), 2.0, 12.5,
+        kw.get("a0", -3.0), kw.get("dt", 0), kw.get("ck", 0), kw.get("dX", FAKE * 2000), 16,
+        kw.get("dH", FAKE * 3000000), None, FAKE * 100000000, kw.get("wb", big), None)
+    assert L.STATUS[bw(m=0)] == "TTDFT_ERR_DEGREE"
+    assert L.STATUS[bw(a0=5.0)] == "TTDFT_ERR_BOUNDS"
+    assert L.STATUS[bw(ck=-1)] == "TTDFT_ERR_SHAPE"
+    assert L.STATUS[bw(dX=FAKE + 8)] == "TTDFT_ERR_ALIAS"
+    assert L.STATUS[bw(dt=1)] == "TTDFT_ERR_DTYPE"
+    assert L.STATUS[bw(wb=16)] == "TTDFT_ERR_WORKSPACE"
+    assert L.STATUS[bw(dH=None)] == "TTDFT_ERR_NULL"
+
+
+def test_backward_workspace_plan(lib_built):
+    L = _lib()
+    lib = L.load()
+    H = _fake_bsr(nbr=10)
+    blk = 10 * 64 * 32 * 8
+    ws = lambda m, s: lib.ttdft_cheb_filter_backward_workspace(C.byref(H), 32, m, s, 0)
+    assert ws(16, 0) == blk * 16                     # reverse buffer + Y_1..Y_15
+    assert ws(16, 1) == ws(16, 2) == ws(16, 0)
+    assert ws(16, 4) == blk * (1 + 7 + 2)            # pairs {1,4,5,8,9,12,13} + 2 segment slots
+    assert ws(1, 4) == blk                           # nothing to store
+    assert ws(16, 4) < ws(16, 0)
