@@ -8,11 +8,12 @@
 // contracted on the matrix cores and the recurrence update is applied in the
 // epilogue, so Yk, Yprev and Yout each cross HBM once per step.
 //
-// Work decomposition: one work-group (4 waves) owns one block row B and one
-// column tile of NV = 64 vectors; it walks the (at most 27) tiles of B, staging
-// the H tile and the matching Yk row panel in LDS, and accumulates in MFMA
+// Work decomposition: one work-group owns one block row B and one column tile
+// of vectors and walks the (at most 27) tiles of B, accumulating in matrix-core
 // registers.  Each output element is produced by exactly one work-group, so
-// results are deterministic (no atomics).
+// results are deterministic (no atomics).  FP64 uses the pipelined kernel
+// cheb_step_f64_pipe; FP32 uses the generic LDS-staged kernel; BF16 tiles use
+// the 16x16x32 bf16 op.
 #include "ttdft_internal.h"
 
 namespace ttdft {
@@ -117,6 +118,124 @@ __global__ __launch_bounds__(THREADS) void cheb_step_mfma4(
   }
 }
 
+// FP64 fast path.  8 waves per work-group; the work-group owns block row B and
+// 128 vectors, wave w the 64 x 16 output slab of vectors 16w .. 16w+15.
+//  - A operand (H tile): double-buffered in LDS in matrix-core fragment order,
+//    element H[16*mb + (l & 15)][4*kk + (l >> 4)] at sH[buf][kk][mb][l], so each
+//    fragment read is 64 consecutive doubles; the next tile is fetched into
+//    registers while the current one is contracted (one barrier per tile).
+//  - B operand (Y_k panel): each wave reads its own 16 vectors straight from
+//    global memory into registers, half a tile (8 k-steps) ahead of use.
+constexpr int F64_NV = 128, F64_THREADS = 512, F64_S = 65;   // fragment row stride (+1 pad)
+
+__device__ inline int64_t group_order(int64_t g, int64_t G, int64_t C) {
+  // hardware ids go round-robin over 8 XCDs; give each XCD C consecutive logical
+  // ids (the column tiles of one block row share that XCD's L2), the 8 XCDs
+  // working on neighbouring block rows at the same time
+  const int64_t span = 8 * C, full = (G / span) * span;
+  if (g >= full) return g;
+  return (g / span) * span + (g % 8) * C + (g / 8) % C;
+}
+
+__global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_f64_pipe(
+    const int32_t *__restrict__ rowptr, const int32_t *__restrict__ tcol,
+    const double *__restrict__ vals, const double *__restrict__ Yk, int64_t ldk,
+    const double *__restrict__ Yp, int64_t ldp, double *Yo, int64_t ldo, int64_t n_vec,
+    int64_t n_ct, int64_t n_block_rows, int64_t cgroup, int64_t n_wg, double alpha, double c,
+    double beta) {
+  __shared__ double sH[2][16 * 4 * F64_S];
+  const int64_t L = group_order(blockIdx.x, n_wg, cgroup);
+  // logical id -> (column group, block row, column tile inside the group)
+  const int64_t per_group = n_block_rows * cgroup;
+  const int64_t cg = L / per_group, rem = L % per_group;
+  const int64_t B = rem / cgroup;
+  const int64_t ct = cg * cgroup + rem % cgroup;
+  if (ct >= n_ct) return;        // last group may be partial (whole work-group exits)
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t col = ct * F64_NV + 16 * w + (lane & 15);
+  const bool col_ok = col < n_vec;
+  const int krow = lane >> 4;    // row of the 4-row k-step this lane loads
+
+  v4d acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = v4d{0, 0, 0, 0};
+
+  const int t_begin = rowptr[B], t_end = rowptr[B + 1];
+  double hreg[4], b0[4], b1[4];
+
+  // next H tile: half h (rows 32h .. 32h+31) into registers, then into LDS
+  auto load_h = [&](int t, int h) {
+    const double *Ht = vals + (int64_t)t * kTileElems + 2048 * h;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) hreg[q] = Ht[tid + F64_THREADS * q];
+  };
+  auto store_h = [&](int buf, int h) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = 2048 * h + tid + F64_THREADS * q, r = idx >> 6, cc = idx & 63;
+      const int kk = cc >> 2, mb = r >> 4, fl = (r & 15) + 16 * (cc & 3);
+      sH[buf][(kk * 4 + mb) * F64_S + fl] = hreg[q];
+    }
+  };
+  // quarter qq (k-steps 4qq .. 4qq+3, panel rows 16qq .. 16qq+15) of the Y_k panel of tile t
+  auto load_b = [&](int t, int qq, double (&dst)[4]) {
+    const double *Xp = Yk + ((int64_t)tcol[t] * 64 + 16 * qq + krow) * ldk + col;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = col_ok ? Xp[(int64_t)(4 * q) * ldk] : 0.0;
+  };
+  auto mma_quarter = [&](const double *sA, int qq, const double (&bq)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kk = 4 * qq + q;
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+        acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[(kk * 4 + mb) * F64_S + lane], bq[q], acc[mb], 0, 0, 0);
+    }
+  };
+
+  if (t_begin < t_end) {
+    load_b(t_begin, 0, b0);
+    load_b(t_begin, 1, b1);
+    load_h(t_begin, 0);
+    store_h(0, 0);
+    load_h(t_begin, 1);
+    store_h(0, 1);
+    __syncthreads();
+  }
+  int buf = 0;
+  for (int t = t_begin; t < t_end; ++t) {
+    const bool more = t + 1 < t_end;
+    const double *sA = sH[buf];
+    if (more) load_h(t + 1, 0);
+    mma_quarter(sA, 0, b0);
+    load_b(t, 2, b0);
+    if (more) store_h(buf ^ 1, 0);
+    mma_quarter(sA, 1, b1);
+    load_b(t, 3, b1);
+    if (more) load_h(t + 1, 1);
+    mma_quarter(sA, 2, b0);
+    if (more) load_b(t + 1, 0, b0);
+    if (more) store_h(buf ^ 1, 1);
+    mma_quarter(sA, 3, b1);
+    if (more) load_b(t + 1, 1, b1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  if (!col_ok) return;
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t grow = B * 64 + 16 * mb + (lane >> 4) + 4 * q;
+      const double y = Yk[grow * ldk + col];
+      double out = alpha * (acc[mb][q] - c * y);
+      if (beta != 0.0) out -= beta * Yp[grow * ldp + col];
+      Yo[grow * ldo + col] = out;
+    }
+  }
+}
+
 // BF16 H tiles with FP32 or BF16 iterates; FP32 accumulation on the
 // 16x16x32 bf16 matrix op.  Lane l supplies A[l%16][8*(l/16) .. +7] and
 // B[8*(l/16) .. +7][l%16]; output item t is D[4*(l/16)+t][l%16].
@@ -200,9 +319,15 @@ hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, con
   if (n_wg > 0x7fffffff) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)n_wg), block(THREADS);
   if (H.dtype == TTDFT_F64) {
-    hipLaunchKernelGGL(cheb_step_mfma4<double>, grid, block, 0, s, H.tile_rowptr, H.tile_col,
-                       (const double *)H.vals, (const double *)Yk, ldk, (const double *)Yp, ldp,
-                       (double *)Yo, ldo, n_vec, n_ct, n_wg, alpha, c, beta);
+    const int64_t ct64 = (n_vec + F64_NV - 1) / F64_NV;
+    const int64_t cgroup = std::min<int64_t>(ct64, 2);
+    const int64_t n_groups = (ct64 + cgroup - 1) / cgroup;
+    const int64_t wg = n_groups * H.n_block_rows * cgroup;
+    if (wg > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(cheb_step_f64_pipe, dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
+                       H.tile_rowptr, H.tile_col, (const double *)H.vals, (const double *)Yk, ldk,
+                       (const double *)Yp, ldp, (double *)Yo, ldo, n_vec, ct64, H.n_block_rows,
+                       cgroup, wg, alpha, c, beta);
   } else if (H.dtype == TTDFT_F32) {
     hipLaunchKernelGGL(cheb_step_mfma4<float>, grid, block, 0, s, H.tile_rowptr, H.tile_col,
                        (const float *)H.vals, (const float *)Yk, ldk, (const float *)Yp, ldp,
