@@ -26,6 +26,21 @@ METRIC = "Chebyshev-filter GFLOP/s + HBM GB/s (% roofline); mixed vs FP64 at ≤
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # dense MFMA peaks, MI355X
 PEAK_HBM_GBS = 8000.0
 
+# HBM-side bytes per launch of the dominant kernel from the two rocprofv3 counter
+# passes (FETCH_SIZE, WRITE_SIZE), calibrated against a plain copy of known size;
+# see profiles/cheb_step_f64_lattice60_h4_n2048_m20_bytes.md.  Valid only while the
+# kernel source is the one that was profiled.
+COUNTED_TRAFFIC = {
+    ("f64", "lattice60_h4_n2048_m20"): {"read_bytes": 111.49e9, "write_bytes": 3.539e9,
+                                        "kernel_sha256_16": "f6c7b3d66daecc34"},
+}
+
+
+def kernel_source_sha16():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2110_15853_amd", "csrc", "cheb_step.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
 
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
@@ -64,7 +79,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the build has no multi-GPU path "
-              "(the filter shards by columns with no communication; see DESIGN.md).",
+              "(the filter shards by columns with no communication).",
               file=sys.stderr)
         sys.exit(2)
 
@@ -138,7 +153,9 @@ def main():
     nnz = len(d)
     n = cfg.n
     alg_flops_launch = 2.0 * nnz * n                      # one H*Y_k product
-    issued_flops_launch = 2.0 * H.n_tiles * 4096 * n       # dense 64x64 tiles on the matrix cores
+    # matrix-core work actually issued: 16x4 sub-blocks whose fragment-mask bit is set
+    frag_bits = int(sum(bin(int(v)).count("1") for v in H.frag_mask.cpu().numpy().view(np.uint64)))
+    issued_flops_launch = 2.0 * frag_bits * 64 * n
     elt = Xb.element_size()
     h_bytes = H.vals.numel() * H.vals.element_size() + 4 * (H.n_tiles + H.n_block_rows + 1)
     alg_bytes_launch = h_bytes + 3.0 * H.rows * n * elt    # read Y_k, Y_{k-1}, write Y_{k+1}
@@ -147,6 +164,10 @@ def main():
     value = alg_flops_launch * cfg.m / filt_s / 1e9
     peak = PEAK_TFLOPS[args.precision]
     achieved = alg_flops_launch / launch_s / 1e12
+    counted = COUNTED_TRAFFIC.get((args.precision, cfg.name))
+    traffic = None
+    if counted and counted["kernel_sha256_16"] == kernel_source_sha16():
+        traffic = counted["read_bytes"] + counted["write_bytes"]
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -172,9 +193,11 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "cheb_step_f64_pipe" if args.precision == "f64"
                      else ("cheb_step_mfma4<float>" if args.precision == "f32" else "cheb_step_bf16<float>"),
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "frac": round(achieved / peak, 4), "traffic": traffic,
                      "per_launch": {"alg_flops": alg_flops_launch, "alg_bytes": alg_bytes_launch,
-                                    "avg_launch_ms": round(launch_s * 1e3, 4)}},
+                                    "issued_flops": issued_flops_launch,
+                                    "avg_launch_ms": round(launch_s * 1e3, 4),
+                                    "traffic_unit": "bytes (L2-miss reads + writes, counter-calibrated)"}},
     }
     if not args.no_cpu_baseline:
         import oracle

@@ -71,6 +71,10 @@ typedef struct {
   const int32_t *tile_col;     /* device [n_tiles]: block column of each tile, ascending in a row */
   const void *vals;            /* device [n_tiles][64][64] row-major values, dtype below       */
   ttdft_dtype dtype;
+  const uint64_t *frag_mask;   /* device [n_tiles] or NULL: bit (4*kk + mb) set when the 16x4
+                                  sub-block rows 16mb..16mb+15, columns 4kk..4kk+3 of the tile
+                                  holds a stored entry; clear bits are skipped by the
+                                  matrix-core contraction.  NULL = contract every sub-block.  */
 } ttdft_bsr;
 
 /* ---------------------------------------------------------------- host-side builder */
@@ -93,14 +97,17 @@ ttdft_status ttdft_bsr_plan(int32_t r, const int64_t *rowptr, const int32_t *col
  *   perm[64*n_block_rows]: blocked row -> natural row, or -1 for a padding row,
  *   entry_slot[nnz] (may be NULL): flat index into vals of each CSR entry,
  *   mask[n_tiles*64] (may be NULL): bit j of word (t*64 + i) set when entry
- *   (i, j) of tile t is a stored CSR entry.
+ *   (i, j) of tile t is a stored CSR entry,
+ *   frag_mask[n_tiles] (may be NULL): bit (4*kk + mb) set when the 16x4
+ *   sub-block (rows 16mb.., columns 4kk..) of tile t holds a stored entry.
  * The lattice is padded to a multiple of 4 per axis with zero rows/columns.
  * Errors: as ttdft_bsr_plan, plus TTDFT_ERR_DTYPE.
  */
 ttdft_status ttdft_bsr_build(int32_t r, const int64_t *rowptr, const int32_t *col,
                              const double *val, ttdft_dtype dtype,
                              int32_t *tile_rowptr, int32_t *tile_col, void *vals,
-                             int64_t *perm, int64_t *entry_slot, uint64_t *mask);
+                             int64_t *perm, int64_t *entry_slot, uint64_t *mask,
+                             uint64_t *frag_mask);
 
 /* ---------------------------------------------------------------- step 1: Chebyshev filter */
 

@@ -26,7 +26,7 @@ class TtdftError(RuntimeError):
 class Bsr(C.Structure):
     _fields_ = [("n_block_rows", C.c_int64), ("n_tiles", C.c_int64),
                 ("tile_rowptr", C.c_void_p), ("tile_col", C.c_void_p),
-                ("vals", C.c_void_p), ("dtype", C.c_int)]
+                ("vals", C.c_void_p), ("dtype", C.c_int), ("frag_mask", C.c_void_p)]
 
 
 def library_path() -> str:
@@ -39,7 +39,7 @@ _BSRP = C.POINTER(Bsr)
 # name -> (restype, argtypes); mirrors include/ttdft.h
 SIGNATURES = {
     "ttdft_bsr_plan": (_INT, [_I32, _P, _P, _P, _P]),
-    "ttdft_bsr_build": (_INT, [_I32, _P, _P, _P, _INT, _P, _P, _P, _P, _P, _P]),
+    "ttdft_bsr_build": (_INT, [_I32, _P, _P, _P, _INT, _P, _P, _P, _P, _P, _P, _P]),
     "ttdft_cheb_step": (_INT, [_BSRP, _P, _I64, _P, _I64, _P, _I64, _I64, _D, _D, _D, _INT, _P]),
     "ttdft_cheb_filter_workspace": (_SZ, [_BSRP, _I64, _INT]),
     "ttdft_cheb_filter": (_INT, [_BSRP, _P, _I64, _P, _I64, _I64, _I32, _D, _D, _D, _INT, _P,

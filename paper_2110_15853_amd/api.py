@@ -58,14 +58,17 @@ class BsrMatrix:
     entry_slot: np.ndarray      # host: flat vals index of each CSR entry
     mask: torch.Tensor          # [n_tiles*64] uint64 stored as int64
     dtype: int
+    frag_mask: torch.Tensor = None   # [n_tiles] uint64 stored as int64; None = no skipping
+    skip_zero_fragments: bool = True
 
     @property
     def rows(self) -> int:
         return 64 * self.n_block_rows
 
     def c_struct(self) -> Bsr:
+        fm = self.frag_mask.data_ptr() if (self.frag_mask is not None and self.skip_zero_fragments) else None
         return Bsr(self.n_block_rows, self.n_tiles, self.tile_rowptr.data_ptr(),
-                   self.tile_col.data_ptr(), self.vals.data_ptr(), self.dtype)
+                   self.tile_col.data_ptr(), self.vals.data_ptr(), self.dtype, fm)
 
 
 def bsr_build(indptr, indices, data, r: int, dtype=torch.float64, device="cuda") -> BsrMatrix:
@@ -83,9 +86,10 @@ def bsr_build(indptr, indices, data, r: int, dtype=torch.float64, device="cuda")
     perm = np.empty(nbr * 64, np.int64)
     slot = np.empty(len(data), np.int64)
     mask = np.empty(nt * 64, np.uint64)
+    fmask = np.empty(max(nt, 1), np.uint64)
     _lib.call("ttdft_bsr_build", r, _np_ptr(indptr), _np_ptr(indices), _np_ptr(data), code,
               _np_ptr(tptr), _np_ptr(tcol), _np_ptr(vals), _np_ptr(perm), _np_ptr(slot),
-              _np_ptr(mask))
+              _np_ptr(mask), _np_ptr(fmask))
     N = r ** 3
     inv = np.empty(N, np.int64)
     real = perm >= 0
@@ -100,7 +104,8 @@ def bsr_build(indptr, indices, data, r: int, dtype=torch.float64, device="cuda")
                      inv_perm=torch.from_numpy(inv).to(device),
                      entry_slot=slot,
                      mask=torch.from_numpy(mask.view(np.int64)).to(device),
-                     dtype=code)
+                     dtype=code,
+                     frag_mask=torch.from_numpy(fmask[:nt].view(np.int64)).to(device))
 
 
 def gather_rows(src: torch.Tensor, perm: torch.Tensor, rows_dst: int) -> torch.Tensor:

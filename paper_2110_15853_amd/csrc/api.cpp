@@ -214,7 +214,7 @@ ttdft_status ttdft_bsr_plan(int32_t r, const int64_t *rowptr, const int32_t *col
 ttdft_status ttdft_bsr_build(int32_t r, const int64_t *rowptr, const int32_t *col,
                              const double *val, ttdft_dtype dtype, int32_t *tile_rowptr,
                              int32_t *tile_col, void *vals, int64_t *perm, int64_t *entry_slot,
-                             uint64_t *mask) {
+                             uint64_t *mask, uint64_t *frag_mask) {
   if (!val || !tile_rowptr || !tile_col || !vals || !perm)
     return fail(TTDFT_ERR_NULL, "an output or val pointer is NULL");
   if (!valid_dtype(dtype)) return fail(TTDFT_ERR_DTYPE, "dtype %d unknown", (int)dtype);
@@ -229,6 +229,7 @@ ttdft_status ttdft_bsr_build(int32_t r, const int64_t *rowptr, const int32_t *co
   std::copy(tcol.begin(), tcol.end(), tile_col);
   std::memset(vals, 0, (size_t)nt * kTileElems * dtype_size(dtype));
   if (mask) std::memset(mask, 0, (size_t)nt * 64 * sizeof(uint64_t));
+  if (frag_mask) std::memset(frag_mask, 0, (size_t)nt * sizeof(uint64_t));
   for (int64_t p = 0; p < NB * 64; ++p) perm[p] = -1;
   for (int64_t I = 0; I < N; ++I) {
     int64_t b, l;
@@ -249,6 +250,7 @@ ttdft_status ttdft_bsr_build(int32_t r, const int64_t *rowptr, const int32_t *co
       }
       if (entry_slot) entry_slot[p] = slot;
       if (mask) mask[t * 64 + l] |= (uint64_t)1 << lc;
+      if (frag_mask) frag_mask[t] |= (uint64_t)1 << (4 * (lc >> 2) + (l >> 4));
     }
   }
   return ok();

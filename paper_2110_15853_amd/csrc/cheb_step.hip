@@ -142,7 +142,7 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_f64_pipe(
     const double *__restrict__ vals, const double *__restrict__ Yk, int64_t ldk,
     const double *__restrict__ Yp, int64_t ldp, double *Yo, int64_t ldo, int64_t n_vec,
     int64_t n_ct, int64_t n_block_rows, int64_t cgroup, int64_t n_wg, double alpha, double c,
-    double beta) {
+    double beta, const uint64_t *__restrict__ frag_mask) {
   __shared__ double sH[2][16 * 4 * F64_S];
   const int64_t L = group_order(blockIdx.x, n_wg, cgroup);
   // logical id -> (column group, block row, column tile inside the group)
@@ -183,13 +183,16 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_f64_pipe(
 #pragma unroll
     for (int q = 0; q < 4; ++q) dst[q] = col_ok ? Xp[(int64_t)(4 * q) * ldk] : 0.0;
   };
-  auto mma_quarter = [&](const double *sA, int qq, const double (&bq)[4]) {
+  // all-zero 16x4 sub-blocks of the tile (bit clear in fm) are skipped; fm is
+  // uniform over the work-group, so the branch costs no divergence
+  auto mma_quarter = [&](const double *sA, int qq, const double (&bq)[4], uint64_t fm) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int kk = 4 * qq + q;
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb)
-        acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[(kk * 4 + mb) * F64_S + lane], bq[q], acc[mb], 0, 0, 0);
+        if ((fm >> (kk * 4 + mb)) & 1ull)
+          acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[(kk * 4 + mb) * F64_S + lane], bq[q], acc[mb], 0, 0, 0);
     }
   };
 
@@ -206,17 +209,18 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_f64_pipe(
   for (int t = t_begin; t < t_end; ++t) {
     const bool more = t + 1 < t_end;
     const double *sA = sH[buf];
+    const uint64_t fm = frag_mask ? frag_mask[t] : ~0ull;
     if (more) load_h(t + 1, 0);
-    mma_quarter(sA, 0, b0);
+    mma_quarter(sA, 0, b0, fm);
     load_b(t, 2, b0);
     if (more) store_h(buf ^ 1, 0);
-    mma_quarter(sA, 1, b1);
+    mma_quarter(sA, 1, b1, fm);
     load_b(t, 3, b1);
     if (more) load_h(t + 1, 1);
-    mma_quarter(sA, 2, b0);
+    mma_quarter(sA, 2, b0, fm);
     if (more) load_b(t + 1, 0, b0);
     if (more) store_h(buf ^ 1, 1);
-    mma_quarter(sA, 3, b1);
+    mma_quarter(sA, 3, b1, fm);
     if (more) load_b(t + 1, 1, b1);
     __syncthreads();
     buf ^= 1;
@@ -327,7 +331,7 @@ hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, con
     hipLaunchKernelGGL(cheb_step_f64_pipe, dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
                        H.tile_rowptr, H.tile_col, (const double *)H.vals, (const double *)Yk, ldk,
                        (const double *)Yp, ldp, (double *)Yo, ldo, n_vec, ct64, H.n_block_rows,
-                       cgroup, wg, alpha, c, beta);
+                       cgroup, wg, alpha, c, beta, H.frag_mask);
   } else if (H.dtype == TTDFT_F32) {
     hipLaunchKernelGGL(cheb_step_mfma4<float>, grid, block, 0, s, H.tile_rowptr, H.tile_col,
                        (const float *)H.vals, (const float *)Yk, ldk, (const float *)Yp, ldp,

@@ -40,7 +40,7 @@ def _lib():
 
 
 def _fake_bsr(nbr=8, nt=64, dtype=0):
-    return _lib().Bsr(nbr, nt, FAKE, FAKE, FAKE, dtype)
+    return _lib().Bsr(nbr, nt, FAKE, FAKE, FAKE, dtype, None)
 
 
 def _filter(**kw):
@@ -112,14 +112,15 @@ def _bsr_host(r, h, dtype_code, seed=0):
     tptr, tcol = np.empty(nbr + 1, np.int32), np.empty(nt, np.int32)
     vals = np.empty(nt * 4096, {0: np.float64, 1: np.float32, 2: np.uint16}[dtype_code])
     perm, slot, mask = np.empty(nbr * 64, np.int64), np.empty(len(d), np.int64), np.empty(nt * 64, np.uint64)
+    fmask = np.empty(nt, np.uint64)
     assert lib.ttdft_bsr_build(r, P(ip), P(ix), P(d), dtype_code, P(tptr), P(tcol), P(vals), P(perm),
-                               P(slot), P(mask)) == 0
-    return (ip, ix, d, N), (nbr, nt, tptr, tcol, vals, perm, slot, mask)
+                               P(slot), P(mask), P(fmask)) == 0
+    return (ip, ix, d, N), (nbr, nt, tptr, tcol, vals, perm, slot, mask, fmask)
 
 
 @pytest.mark.parametrize("r,h", [(4, 1), (6, 2), (10, 3), (8, 4), (5, 3)])
 def test_bsr_builder_roundtrip(lib_built, r, h):
-    (ip, ix, d, N), (nbr, nt, tptr, tcol, vals, perm, slot, mask) = _bsr_host(r, h, 0)
+    (ip, ix, d, N), (nbr, nt, tptr, tcol, vals, perm, slot, mask, fmask) = _bsr_host(r, h, 0)
     nb = (r + 3) // 4
     assert nbr == nb ** 3 and tptr[-1] == nt
     Hd = oracle.csr_from_arrays(ip, ix, d, N).toarray()
@@ -141,6 +142,10 @@ def test_bsr_builder_roundtrip(lib_built, r, h):
     weights = (np.uint64(1) << np.arange(64, dtype=np.uint64))
     words = (bits.reshape(nt * 64, 64).astype(np.uint64) * weights).sum(axis=1, dtype=np.uint64)
     np.testing.assert_array_equal(words, mask)
+    # fragment mask: bit 4*kk + mb set iff the 16x4 sub-block holds a stored entry
+    sub = bits.reshape(nt, 4, 16, 16, 4).any(axis=(2, 4))          # [t][mb][kk]
+    fw = (sub.transpose(0, 2, 1).reshape(nt, 64).astype(np.uint64) * weights).sum(axis=1, dtype=np.uint64)
+    np.testing.assert_array_equal(fw, fmask)
     # lattice blocking: every tile couples blocks at most one block apart per axis when h <= 4
     for B in range(nbr):
         bi, bj, bk = B // (nb * nb), (B // nb) % nb, B % nb
@@ -152,9 +157,9 @@ def test_bsr_builder_roundtrip(lib_built, r, h):
 
 def test_bsr_builder_low_precision_rounding(lib_built):
     import torch
-    (ip, ix, d, N), (_, _, _, _, v32, _, slot, _) = _bsr_host(5, 2, 1)
+    (ip, ix, d, N), (_, _, _, _, v32, _, slot, _, _) = _bsr_host(5, 2, 1)
     np.testing.assert_array_equal(v32[slot], d.astype(np.float32))
-    (ip, ix, d, N), (_, _, _, _, v16, _, slot, _) = _bsr_host(5, 2, 2)
+    (ip, ix, d, N), (_, _, _, _, v16, _, slot, _, _) = _bsr_host(5, 2, 2)
     ref = torch.from_numpy(d.astype(np.float32)).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
     np.testing.assert_array_equal(v16[slot], ref)
 

@@ -87,3 +87,20 @@ def test_filter_special_case_shift_identity():
         tau = (A0 - c) / ((B - A) / 2)
         expect = np.cos(m * np.pi / 2) / oracle.chebyshev_T(m, tau) * X
         np.testing.assert_allclose(Y, expect, atol=1e-15 * np.abs(X).max() / abs(oracle.chebyshev_T(m, tau)))
+
+
+@pytest.mark.parametrize("r,h", [(12, 4), (12, 3), (10, 2)])
+def test_zero_fragment_skipping_is_exact(r, h):
+    # skipping all-zero 16x4 sub-blocks removes only products with zero operands
+    torch, P = require_gpu()
+    Hc, Hb, X = make_case(r, h, 150, seed=9)
+    Xb = P.to_blocked(torch.from_numpy(X).cuda(), Hb)
+    Y1 = P.cheb_filter(Hb, Xb, 6, A, B, A0)
+    Hb.skip_zero_fragments = False
+    Y0 = P.cheb_filter(Hb, Xb, 6, A, B, A0)
+    Hb.skip_zero_fragments = True
+    assert torch.equal(Y0, Y1)
+    fm = Hb.frag_mask.cpu().numpy().view(np.uint64)
+    skipped = 1 - np.mean([bin(int(v)).count("1") for v in fm]) / 64
+    print(f"r={r} h={h}: {skipped:.1%} of matrix-core sub-blocks skipped", flush=True)
+    assert skipped > 0
