@@ -62,6 +62,57 @@ def cpu_baseline(Hc, X, cfg, n_cols):
             "host_cpus": os.cpu_count(), "host": platform.processor() or platform.machine()}
 
 
+def mixed_precision_report(P, torch, ip, ix, d, cfg, H64, Xb64, keep_frac=1800 / 2048, reps=3):
+    """Low-precision filters (FP32; BF16 H with FP32 iterates) followed by the
+    FP64 Rayleigh-Ritz with FP64 H, against the FP64 pipeline from the same
+    start block: timing of the filters, and the error of the lowest Ritz values
+    and the largest principal angle between the Ritz subspaces, from a random
+    start (cold) and from the FP64 Ritz vectors of one previous pass (warm)."""
+    keep = int(round(keep_frac * cfg.n))
+    out = {"keep": keep}
+
+    def filt(H, X):
+        return P.cheb_filter(H, X, cfg.m, cfg.a, cfg.b, cfg.a0)
+
+    def time_filter(H, X):
+        Y = filt(H, X)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            filt(H, X)
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps, Y
+
+    def angle(U, V):
+        S = torch.linalg.svdvals((U.T @ V).cpu())
+        return float(torch.arccos(torch.clamp(S.min(), -1.0, 1.0)))
+
+    t64, _ = time_filter(H64, Xb64)
+    out["f64_filter_ms"] = round(t64, 3)
+    lam_c, psi_c = P.rayleigh_ritz(H64, filt(H64, Xb64))
+    Xw = psi_c.clone()
+    lam_w, psi_w = P.rayleigh_ritz(H64, filt(H64, Xw))
+    for name, hdt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        H = P.bsr_build(ip, ix, d, cfg.r, dtype=hdt, device="cuda")
+        Xl = P.cast(Xb64, torch.float32)
+        tl, _ = time_filter(H, Xl)
+        rec = {"filter_ms": round(tl, 3), "speedup_vs_f64_filter": round(t64 / tl, 3),
+               "alg_gflops": round(2.0 * len(d) * cfg.n * cfg.m / (tl / 1e3) / 1e9, 1)}
+        for regime, X0, lam_ref, psi_ref in (("cold", Xl, lam_c, psi_c),
+                                             ("warm", P.cast(Xw, torch.float32), lam_w, psi_w)):
+            lam, psi = P.rayleigh_ritz(H64, filt(H, X0))
+            err = float((lam[:keep] - lam_ref[:keep]).abs().max())
+            rec[regime] = {"max_ritz_err_Ha": err, "max_angle_rad": angle(psi_ref[:, :keep], psi[:, :keep]),
+                           "meets_1e-6_Ha": err <= 1e-6}
+        out[name] = rec
+        del H
+        torch.cuda.empty_cache()
+        log(f"mixed {name}: {rec}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +123,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=8)
     ap.add_argument("--no-rr", action="store_true", help="time the filter alone")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the reduced-precision filters and their Ritz-value errors")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain device copy of the X block (known bytes) before the timed "
                          "steps, to scale hardware byte counters")
@@ -199,6 +252,10 @@ def main():
                                     "avg_launch_ms": round(launch_s * 1e3, 4),
                                     "traffic_unit": "bytes (L2-miss reads + writes, counter-calibrated)"}},
     }
+    if not args.no_mixed and args.precision == "f64" and do_rr:
+        del rr_work, work
+        torch.cuda.empty_cache()
+        out["mixed_vs_f64"] = mixed_precision_report(P, torch, ip, ix, d, cfg, H, Xb)
     if not args.no_cpu_baseline:
         import oracle
         log("CPU baseline (oracle) ...")

@@ -11,9 +11,8 @@
 // Work decomposition: one work-group owns one block row B and one column tile
 // of vectors and walks the (at most 27) tiles of B, accumulating in matrix-core
 // registers.  Each output element is produced by exactly one work-group, so
-// results are deterministic (no atomics).  FP64 uses the pipelined kernel
-// cheb_step_f64_pipe; FP32 uses the generic LDS-staged kernel; BF16 tiles use
-// the 16x16x32 bf16 op.
+// results are deterministic (no atomics).  FP64 and FP32 use the pipelined
+// kernel cheb_step_pipe<T>; BF16 tiles use the LDS-staged 16x16x32 bf16 kernel.
 #include "ttdft_internal.h"
 
 namespace ttdft {
@@ -53,72 +52,7 @@ template <> struct Mfma4<float> {
   static __device__ inline int row(int lane, int t) { return 4 * (lane >> 4) + t; }
 };
 
-// T = storage and arithmetic type of H and Y (double: FP64 MFMA; float: FP32 MFMA).
-template <typename T>
-__global__ __launch_bounds__(THREADS) void cheb_step_mfma4(
-    const int32_t *__restrict__ rowptr, const int32_t *__restrict__ tcol,
-    const T *__restrict__ vals, const T *__restrict__ Yk, int64_t ldk,
-    const T *__restrict__ Yp, int64_t ldp, T *Yo, int64_t ldo, int64_t n_vec, int64_t n_ct,
-    int64_t n_wg, T alpha, T c, T beta) {
-  using M = Mfma4<T>;
-  __shared__ T sH[64][65];
-  __shared__ T sX[64][NV + 1];
-
-  const int64_t g = xcd_remap(blockIdx.x, n_wg);
-  const int64_t B = g / n_ct, ct = g % n_ct;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t col0 = ct * NV;
-
-  typename M::acc_t acc[4];
-  for (int j = 0; j < 4; ++j) acc[j] = typename M::acc_t{0, 0, 0, 0};
-
-  const int t_begin = rowptr[B], t_end = rowptr[B + 1];
-  for (int t = t_begin; t < t_end; ++t) {
-    const int64_t Bc = tcol[t];
-    const T *Ht = vals + (int64_t)t * kTileElems;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = tid + THREADS * q;
-      sH[idx >> 6][idx & 63] = Ht[idx];
-    }
-    const T *Xp = Yk + Bc * 64 * ldk;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = tid + THREADS * q;
-      const int r = idx >> 6, cc = idx & 63;
-      const int64_t col = col0 + cc;
-      sX[r][cc] = col < n_vec ? Xp[(int64_t)r * ldk + col] : T(0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 64; kk += 4) {
-      const T a = sH[16 * w + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-      for (int jb = 0; jb < 4; ++jb) {
-        const T b = sX[kk + (lane >> 4)][16 * jb + (lane & 15)];
-        acc[jb] = M::op(a, b, acc[jb]);
-      }
-    }
-    __syncthreads();
-  }
-
-  // epilogue: Yout = alpha*(acc - c*Yk) - beta*Yprev (row-local, so Yout may be Yprev)
-#pragma unroll
-  for (int jb = 0; jb < 4; ++jb) {
-    const int64_t col = col0 + 16 * jb + (lane & 15);
-    if (col >= n_vec) continue;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int64_t grow = B * 64 + 16 * w + M::row(lane, t);
-      const T y = Yk[grow * ldk + col];
-      T out = alpha * (acc[jb][t] - c * y);
-      if (beta != T(0)) out -= beta * Yp[grow * ldp + col];
-      Yo[grow * ldo + col] = out;
-    }
-  }
-}
-
-// FP64 fast path.  8 waves per work-group; the work-group owns block row B and
+// Pipelined FP64 / FP32 path.  8 waves per work-group; the work-group owns block row B and
 // 128 vectors, wave w the 64 x 16 output slab of vectors 16w .. 16w+15.
 //  - A operand (H tile): double-buffered in LDS in matrix-core fragment order,
 //    element H[16*mb + (l & 15)][4*kk + (l >> 4)] at sH[buf][kk][mb][l], so each
@@ -137,13 +71,16 @@ __device__ inline int64_t group_order(int64_t g, int64_t G, int64_t C) {
   return (g / span) * span + (g % 8) * C + (g / 8) % C;
 }
 
-__global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_f64_pipe(
+// T = double (f64 16x16x4) or float (f32 16x16x4, same operand layouts)
+template <typename T>
+__global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_pipe(
     const int32_t *__restrict__ rowptr, const int32_t *__restrict__ tcol,
-    const double *__restrict__ vals, const double *__restrict__ Yk, int64_t ldk,
-    const double *__restrict__ Yp, int64_t ldp, double *Yo, int64_t ldo, int64_t n_vec,
-    int64_t n_ct, int64_t n_block_rows, int64_t cgroup, int64_t n_wg, double alpha, double c,
-    double beta, const uint64_t *__restrict__ frag_mask) {
-  __shared__ double sH[2][16 * 4 * F64_S];
+    const T *__restrict__ vals, const T *__restrict__ Yk, int64_t ldk,
+    const T *__restrict__ Yp, int64_t ldp, T *Yo, int64_t ldo, int64_t n_vec,
+    int64_t n_ct, int64_t n_block_rows, int64_t cgroup, int64_t n_wg, T alpha, T c,
+    T beta, const uint64_t *__restrict__ frag_mask) {
+  using M = Mfma4<T>;
+  __shared__ T sH[2][16 * 4 * F64_S];
   const int64_t L = group_order(blockIdx.x, n_wg, cgroup);
   // logical id -> (column group, block row, column tile inside the group)
   const int64_t per_group = n_block_rows * cgroup;
@@ -156,16 +93,16 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_f64_pipe(
   const bool col_ok = col < n_vec;
   const int krow = lane >> 4;    // row of the 4-row k-step this lane loads
 
-  v4d acc[4];
+  typename M::acc_t acc[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = v4d{0, 0, 0, 0};
+  for (int j = 0; j < 4; ++j) acc[j] = typename M::acc_t{0, 0, 0, 0};
 
   const int t_begin = rowptr[B], t_end = rowptr[B + 1];
-  double hreg[4], b0[4], b1[4];
+  T hreg[4], b0[4], b1[4];
 
   // next H tile: half h (rows 32h .. 32h+31) into registers, then into LDS
   auto load_h = [&](int t, int h) {
-    const double *Ht = vals + (int64_t)t * kTileElems + 2048 * h;
+    const T *Ht = vals + (int64_t)t * kTileElems + 2048 * h;
 #pragma unroll
     for (int q = 0; q < 4; ++q) hreg[q] = Ht[tid + F64_THREADS * q];
   };
@@ -178,21 +115,21 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_f64_pipe(
     }
   };
   // quarter qq (k-steps 4qq .. 4qq+3, panel rows 16qq .. 16qq+15) of the Y_k panel of tile t
-  auto load_b = [&](int t, int qq, double (&dst)[4]) {
-    const double *Xp = Yk + ((int64_t)tcol[t] * 64 + 16 * qq + krow) * ldk + col;
+  auto load_b = [&](int t, int qq, T (&dst)[4]) {
+    const T *Xp = Yk + ((int64_t)tcol[t] * 64 + 16 * qq + krow) * ldk + col;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) dst[q] = col_ok ? Xp[(int64_t)(4 * q) * ldk] : 0.0;
+    for (int q = 0; q < 4; ++q) dst[q] = col_ok ? Xp[(int64_t)(4 * q) * ldk] : T(0);
   };
   // all-zero 16x4 sub-blocks of the tile (bit clear in fm) are skipped; fm is
   // uniform over the work-group, so the branch costs no divergence
-  auto mma_quarter = [&](const double *sA, int qq, const double (&bq)[4], uint64_t fm) {
+  auto mma_quarter = [&](const T *sA, int qq, const T (&bq)[4], uint64_t fm) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int kk = 4 * qq + q;
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb)
         if ((fm >> (kk * 4 + mb)) & 1ull)
-          acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[(kk * 4 + mb) * F64_S + lane], bq[q], acc[mb], 0, 0, 0);
+          acc[mb] = M::op(sA[(kk * 4 + mb) * F64_S + lane], bq[q], acc[mb]);
     }
   };
 
@@ -208,7 +145,7 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_f64_pipe(
   int buf = 0;
   for (int t = t_begin; t < t_end; ++t) {
     const bool more = t + 1 < t_end;
-    const double *sA = sH[buf];
+    const T *sA = sH[buf];
     const uint64_t fm = frag_mask ? frag_mask[t] : ~0ull;
     if (more) load_h(t + 1, 0);
     mma_quarter(sA, 0, b0, fm);
@@ -231,10 +168,10 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_f64_pipe(
   for (int mb = 0; mb < 4; ++mb) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t grow = B * 64 + 16 * mb + (lane >> 4) + 4 * q;
-      const double y = Yk[grow * ldk + col];
-      double out = alpha * (acc[mb][q] - c * y);
-      if (beta != 0.0) out -= beta * Yp[grow * ldp + col];
+      const int64_t grow = B * 64 + 16 * mb + M::row(lane, q);
+      const T y = Yk[grow * ldk + col];
+      T out = alpha * (acc[mb][q] - c * y);
+      if (beta != T(0)) out -= beta * Yp[grow * ldp + col];
       Yo[grow * ldo + col] = out;
     }
   }
@@ -322,20 +259,23 @@ hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, con
   const int64_t n_wg = H.n_block_rows * n_ct;
   if (n_wg > 0x7fffffff) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)n_wg), block(THREADS);
-  if (H.dtype == TTDFT_F64) {
-    const int64_t ct64 = (n_vec + F64_NV - 1) / F64_NV;
-    const int64_t cgroup = std::min<int64_t>(ct64, 2);
-    const int64_t n_groups = (ct64 + cgroup - 1) / cgroup;
+  if (H.dtype == TTDFT_F64 || H.dtype == TTDFT_F32) {
+    const int64_t ctp = (n_vec + F64_NV - 1) / F64_NV;
+    const int64_t cgroup = std::min<int64_t>(ctp, 2);
+    const int64_t n_groups = (ctp + cgroup - 1) / cgroup;
     const int64_t wg = n_groups * H.n_block_rows * cgroup;
     if (wg > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(cheb_step_f64_pipe, dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
-                       H.tile_rowptr, H.tile_col, (const double *)H.vals, (const double *)Yk, ldk,
-                       (const double *)Yp, ldp, (double *)Yo, ldo, n_vec, ct64, H.n_block_rows,
-                       cgroup, wg, alpha, c, beta, H.frag_mask);
-  } else if (H.dtype == TTDFT_F32) {
-    hipLaunchKernelGGL(cheb_step_mfma4<float>, grid, block, 0, s, H.tile_rowptr, H.tile_col,
-                       (const float *)H.vals, (const float *)Yk, ldk, (const float *)Yp, ldp,
-                       (float *)Yo, ldo, n_vec, n_ct, n_wg, (float)alpha, (float)c, (float)beta);
+    if (H.dtype == TTDFT_F64)
+      hipLaunchKernelGGL(cheb_step_pipe<double>, dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
+                         H.tile_rowptr, H.tile_col, (const double *)H.vals, (const double *)Yk,
+                         ldk, (const double *)Yp, ldp, (double *)Yo, ldo, n_vec, ctp,
+                         H.n_block_rows, cgroup, wg, alpha, c, beta, H.frag_mask);
+    else
+      hipLaunchKernelGGL(cheb_step_pipe<float>, dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
+                         H.tile_rowptr, H.tile_col, (const float *)H.vals, (const float *)Yk,
+                         ldk, (const float *)Yp, ldp, (float *)Yo, ldo, n_vec, ctp,
+                         H.n_block_rows, cgroup, wg, (float)alpha, (float)c, (float)beta,
+                         H.frag_mask);
   } else if (xt == TTDFT_F32) {
     hipLaunchKernelGGL(cheb_step_bf16<float>, grid, block, 0, s, H.tile_rowptr, H.tile_col,
                        (const __bf16 *)H.vals, (const float *)Yk, ldk, (const float *)Yp, ldp,

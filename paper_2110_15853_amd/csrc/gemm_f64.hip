@@ -5,8 +5,10 @@
 //   NN  C = A B     (tall rows x n times a small n x n): Y R^{-1} (step 2) and
 //                   the rotation Psi = X_F Q (step 5).
 // Both share one 128x128 output tile per work-group (4 waves, each a 64x64
-// quadrant of 4x4 MFMA f64 16x16x4 blocks) and stage 32-deep K panels of both
-// operands in LDS, k-major, so every MFMA operand read is 16 consecutive doubles.
+// quadrant of 4x4 MFMA f64 16x16x4 blocks); 16-deep K panels of both operands
+// are double-buffered in LDS, k-major (every operand read is 16 consecutive
+// doubles), with the next panel prefetched into registers during the current
+// panel's contraction (one barrier per panel).
 // The TN product splits K across work-groups; partial tiles are summed in a
 // fixed order by a second kernel, so results are deterministic.
 #include "ttdft_internal.h"
@@ -16,41 +18,110 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 128, BN = 128, BK = 32, THREADS = 256;
-constexpr int LDS_LD = BM + 1;   // +1 double: stride of 258 dwords spreads the banks
+constexpr int BM = 128, BN = 128, BK = 16, THREADS = 256;
+constexpr int LDS_LD = BM + 4;   // row stride 132 doubles: rows 8 banks apart
 
 __device__ inline v4d mfma(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// acc[mi][ni] covers rows 64*wm + 16*mi .. , cols 64*wn + 16*ni .. of the tile
-__device__ inline void mma_panel(const double (*sA)[LDS_LD], const double (*sB)[LDS_LD],
-                                 v4d (&acc)[4][4], int wm, int wn, int lane) {
-#pragma unroll
-  for (int kq = 0; kq < BK; kq += 4) {
-    double a[4], b[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = sA[kq + (lane >> 4)][64 * wm + 16 * i + (lane & 15)];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) b[j] = sB[kq + (lane >> 4)][64 * wn + 16 * j + (lane & 15)];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
-  }
-}
-
 // output item t of lane l in a 16x16 f64 block sits at row (l>>4) + 4t, col l&15
 __device__ inline int out_row(int lane, int t) { return (lane >> 4) + 4 * t; }
 
+// One 128x128 tile, K in panels of 16, double-buffered in LDS with the next
+// panel prefetched into registers; both operands held k-major in LDS.
+// TN: A is K x M (element (k, i) at A[k*lda + i]); NN: A is M x K (A[i*lda + k]).
+// B is always K x N (B[k*ldb + j]).  Wave (wm, wn) owns the 64x64 quadrant.
+template <bool TN> struct Tile {
+  double (*sA)[BK][LDS_LD];
+  double (*sB)[BK][LDS_LD];
+  double ra[8], rb[8];
+  v4d acc[4][4];
+
+  __device__ void load(const double *A, int64_t lda, const double *B, int64_t ldb, int64_t i0,
+                       int64_t j0, int64_t k0, int64_t kend, int64_t M, int64_t N) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + THREADS * q;
+      if (TN) {
+        const int kk = idx / BM, c = idx % BM;
+        const int64_t k = k0 + kk;
+        ra[q] = (k < kend && i0 + c < M) ? A[k * lda + i0 + c] : 0.0;
+      } else {
+        const int r = idx / BK, kk = idx % BK;      // 16 consecutive k of one row
+        const int64_t k = k0 + kk;
+        ra[q] = (k < kend && i0 + r < M) ? A[(i0 + r) * lda + k] : 0.0;
+      }
+      const int kb = idx / BN, c = idx % BN;
+      const int64_t k = k0 + kb;
+      rb[q] = (k < kend && j0 + c < N) ? B[k * ldb + j0 + c] : 0.0;
+    }
+  }
+  __device__ void store(int buf) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + THREADS * q;
+      if (TN) sA[buf][idx / BM][idx % BM] = ra[q];
+      else sA[buf][idx % BK][idx / BK] = ra[q];
+      sB[buf][idx / BN][idx % BN] = rb[q];
+    }
+  }
+  __device__ void compute(int buf, int wm, int wn, int lane) {
+#pragma unroll
+    for (int kq = 0; kq < BK; kq += 4) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = sA[buf][kq + (lane >> 4)][64 * wm + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = sB[buf][kq + (lane >> 4)][64 * wn + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
+    }
+  }
+  // acc = sum over k in [kb, ke) of opA(A)[i][k] B[k][j]
+  __device__ void run(const double *A, int64_t lda, const double *B, int64_t ldb, int64_t i0,
+                      int64_t j0, int64_t kb, int64_t ke, int64_t M, int64_t N) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+    if (kb >= ke) return;
+    load(A, lda, B, ldb, i0, j0, kb, ke, M, N);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+      const bool more = k0 + BK < ke;
+      if (more) load(A, lda, B, ldb, i0, j0, k0 + BK, ke, M, N);
+      compute(buf, wm, wn, lane);
+      if (more) store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+};
+
+// hardware ids are dealt round-robin to the 8 XCDs; give each XCD C consecutive
+// logical ids so work-groups sharing an operand panel share that XCD's L2
+__device__ inline int64_t xcd_group(int64_t g, int64_t G, int64_t C) {
+  const int64_t span = 8 * C, full = (G / span) * span;
+  if (g >= full) return g;
+  return (g / span) * span + (g % 8) * C + (g / 8) % C;
+}
+
 // ---------------------------------------------------------------- C = A^T B, split K
 // grid.x = tile index (lower-triangular pairs when sym), grid.y = split
-__global__ __launch_bounds__(THREADS) void gemm_tn_kernel(
+__global__ __launch_bounds__(THREADS, 2) void gemm_tn_kernel(
     const double *__restrict__ A, int64_t lda, const double *__restrict__ B, int64_t ldb,
     int64_t K, int64_t n, double *__restrict__ partial, int64_t k_per_split, int tiles_n,
     int sym) {
-  __shared__ double sA[BK][LDS_LD];
-  __shared__ double sB[BK][LDS_LD];
+  __shared__ double sA[2][BK][LDS_LD];
+  __shared__ double sB[2][BK][LDS_LD];
   int ti, tj;
   if (sym) {  // linear index over lower-triangular tile pairs (ti >= tj)
     int t = blockIdx.x;
@@ -65,29 +136,11 @@ __global__ __launch_bounds__(THREADS) void gemm_tn_kernel(
   const int64_t i0 = (int64_t)ti * BM, j0 = (int64_t)tj * BN;
   const int64_t kb = (int64_t)blockIdx.y * k_per_split;
   const int64_t ke = min(K, kb + k_per_split);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
-
-  v4d acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0, 0, 0, 0};
-
-  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
-#pragma unroll
-    for (int q = 0; q < BK * BM / THREADS; ++q) {
-      const int idx = tid + THREADS * q;
-      const int kk = idx / BM, c = idx % BM;
-      const int64_t k = k0 + kk;
-      const bool kin = k < ke;
-      sA[kk][c] = (kin && i0 + c < n) ? A[k * lda + i0 + c] : 0.0;
-      sB[kk][c] = (kin && j0 + c < n) ? B[k * ldb + j0 + c] : 0.0;
-    }
-    __syncthreads();
-    mma_panel(sA, sB, acc, wm, wn, lane);
-    __syncthreads();
-  }
-
+  Tile<true> T;
+  T.sA = sA;
+  T.sB = sB;
+  T.run(A, lda, B, ldb, i0, j0, kb, ke, n, n);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
   double *P = partial + (int64_t)blockIdx.y * n * n;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -97,7 +150,7 @@ __global__ __launch_bounds__(THREADS) void gemm_tn_kernel(
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int64_t row = i0 + 64 * wm + 16 * i + out_row(lane, t);
-        if (row < n && col < n) P[row * n + col] = acc[i][j][t];
+        if (row < n && col < n) P[row * n + col] = T.acc[i][j][t];
       }
     }
 }
@@ -127,40 +180,22 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(const double *__rest
 
 // ---------------------------------------------------------------- C = alpha * A B
 // A: rows x K (lda), B: K x N (ldb), C: rows x N (ldc).  upper: B[k][j] = 0 for k > j.
-__global__ __launch_bounds__(THREADS) void gemm_nn_kernel(
+// The column tiles of one row panel of A run on one XCD (they share that panel).
+__global__ __launch_bounds__(THREADS, 2) void gemm_nn_kernel(
     const double *__restrict__ A, int64_t lda, const double *__restrict__ B, int64_t ldb,
     int64_t rows, int64_t K, int64_t N, double alpha, double *__restrict__ C, int64_t ldc,
-    int upper, int tiles_n) {
-  __shared__ double sA[BK][LDS_LD];   // transposed A panel: [k][row]
-  __shared__ double sB[BK][LDS_LD];
-  const int64_t tn = blockIdx.x % tiles_n, tm = blockIdx.x / tiles_n;
+    int upper, int tiles_n, int64_t n_wg) {
+  __shared__ double sA[2][BK][LDS_LD];
+  __shared__ double sB[2][BK][LDS_LD];
+  const int64_t L = xcd_group(blockIdx.x, n_wg, tiles_n);
+  const int64_t tn = L % tiles_n, tm = L / tiles_n;
   const int64_t i0 = tm * BM, j0 = tn * BN;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
   const int64_t kend = upper ? min(K, j0 + BN) : K;
-
-  v4d acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0, 0, 0, 0};
-
-  for (int64_t k0 = 0; k0 < kend; k0 += BK) {
-#pragma unroll
-    for (int q = 0; q < BK * BM / THREADS; ++q) {
-      const int idx = tid + THREADS * q;
-      // A: consecutive threads walk k inside a row (coalesced 256-byte row segments)
-      const int r = idx / BK, kk = idx % BK;
-      const int64_t k = k0 + kk;
-      sA[kk][r] = (i0 + r < rows && k < kend) ? A[(i0 + r) * lda + k] : 0.0;
-      const int kb = idx / BN, c = idx % BN;
-      const int64_t kB = k0 + kb;
-      sB[kb][c] = (kB < kend && j0 + c < N) ? B[kB * ldb + j0 + c] : 0.0;
-    }
-    __syncthreads();
-    mma_panel(sA, sB, acc, wm, wn, lane);
-    __syncthreads();
-  }
-
+  Tile<false> T;
+  T.sA = sA;
+  T.sB = sB;
+  T.run(A, lda, B, ldb, i0, j0, 0, kend, rows, N);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -169,7 +204,7 @@ __global__ __launch_bounds__(THREADS) void gemm_nn_kernel(
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int64_t row = i0 + 64 * wm + 16 * i + out_row(lane, t);
-        if (row < rows && col < N) C[row * ldc + col] = alpha * acc[i][j][t];
+        if (row < rows && col < N) C[row * ldc + col] = alpha * T.acc[i][j][t];
       }
     }
 }
@@ -224,7 +259,7 @@ hipError_t launch_gemm_nn_ex(const double *A, int64_t lda, const double *B, int6
   const int64_t g = tiles_m * tiles_n;
   if (g > 0x7fffffff) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(gemm_nn_kernel, dim3((unsigned)g), dim3(THREADS), 0, s, A, lda, B, ldb,
-                     rows, K, N, alpha, C, ldc, upper ? 1 : 0, tiles_n);
+                     rows, K, N, alpha, C, ldc, upper ? 1 : 0, tiles_n, g);
   return hipGetLastError();
 }
 
