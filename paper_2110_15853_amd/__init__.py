@@ -16,6 +16,9 @@ from .api import (  # noqa: F401
     to_blocked,
     DTYPE_CODES,
     ChebFilter,
+    bsr_astype,
+    chfsi_iteration,
+    updated_bounds,
     cheb_filter_autograd,
     cheb_filter_backward,
     cholqr2,

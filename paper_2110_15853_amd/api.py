@@ -274,3 +274,36 @@ def cheb_filter_autograd(H: BsrMatrix, X: torch.Tensor, m: int, a: float, b: flo
                          ckpt_every: int = 0) -> torch.Tensor:
     """Chebyshev filter that records the adjoint for torch.autograd."""
     return ChebFilter.apply(H.vals, X, H, m, a, b, a0, ckpt_every)
+
+
+def bsr_astype(H: BsrMatrix, dtype: torch.dtype) -> BsrMatrix:
+    """The same blocked matrix with its tile values converted on the device by
+    ttdft_cast (round to nearest even); pattern arrays are shared."""
+    code = DTYPE_CODES[dtype]
+    if code == H.dtype:
+        return H
+    flat = H.vals.reshape(H.n_tiles * 64, 64)
+    vals = cast(flat, dtype).reshape(H.n_tiles, 64, 64)
+    return BsrMatrix(r=H.r, N=H.N, n_block_rows=H.n_block_rows, n_tiles=H.n_tiles,
+                     tile_rowptr=H.tile_rowptr, tile_col=H.tile_col, vals=vals, perm=H.perm,
+                     inv_perm=H.inv_perm, entry_slot=H.entry_slot, mask=H.mask, dtype=code,
+                     frag_mask=H.frag_mask, skip_zero_fragments=H.skip_zero_fragments)
+
+
+def chfsi_iteration(Hf: BsrMatrix, H64: BsrMatrix, X: torch.Tensor, m: int, a: float, b: float,
+                    a0: float, rr_work: torch.Tensor = None):
+    """One pass of Algorithm 1: the filter with Hf (any supported precision) on
+    X, then FP64 Rayleigh-Ritz with H64.  Returns (lambda, Psi, filtered Y)."""
+    Y = cheb_filter(Hf, X, m, a, b, a0)
+    lam, Psi = rayleigh_ritz(H64, Y, work=rr_work)
+    return lam, Psi, Y
+
+
+def updated_bounds(lam: torch.Tensor, b: float):
+    """Bounds for the next pass from the Ritz values of this one: the scaling
+    point a0 moves to the smallest Ritz value and the lower end a of the
+    unwanted interval to the largest, the upper bound b is kept."""
+    lo, hi = float(lam.min()), float(lam.max())
+    if not (lo < hi < b):
+        raise ValueError("Ritz values do not leave a0 < a < b")
+    return lo, hi

@@ -250,6 +250,116 @@ __global__ __launch_bounds__(THREADS) void cheb_step_bf16(
   }
 }
 
+// Pipelined BF16 path: BF16 H tiles, FP32 or BF16 iterates, FP32 accumulation
+// on the 16x16x32 bf16 op.  Same decomposition as cheb_step_pipe (8 waves,
+// 128 vectors, wave w owns vectors 16w .. 16w+15):
+//  - A (H tile, 8 KB): double-buffered in LDS in fragment order, lane l of
+//    fragment (kk, mb) holding H[16mb + (l&15)][32kk + 8(l>>4) .. +7] as one
+//    16-byte read;
+//  - B (Y_k): lane l gathers Y_k[32kk + 8(l>>4) + t][col], t = 0..7, rounds to
+//    bf16 and packs them; the next tile's values are fetched during the current
+//    tile's contraction.
+//  - a 16x32 fragment is skipped when all eight 16x4 sub-blocks it covers are
+//    clear in the fragment mask.
+template <typename TX>
+__global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_bf16_pipe(
+    const int32_t *__restrict__ rowptr, const int32_t *__restrict__ tcol,
+    const __bf16 *__restrict__ vals, const TX *__restrict__ Yk, int64_t ldk,
+    const TX *__restrict__ Yp, int64_t ldp, TX *Yo, int64_t ldo, int64_t n_vec, int64_t n_ct,
+    int64_t n_block_rows, int64_t cgroup, int64_t n_wg, float alpha, float c, float beta,
+    const uint64_t *__restrict__ frag_mask) {
+  __shared__ __attribute__((aligned(16))) __bf16 sH[2][2 * 4 * 64 * 8];   // [buf][kk][mb][lane][8]
+  const int64_t L = group_order(blockIdx.x, n_wg, cgroup);
+  const int64_t per_group = n_block_rows * cgroup;
+  const int64_t cg = L / per_group, rem = L % per_group;
+  const int64_t B = rem / cgroup;
+  const int64_t ct = cg * cgroup + rem % cgroup;
+  if (ct >= n_ct) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t col = ct * F64_NV + 16 * w + (lane & 15);
+  const bool col_ok = col < n_vec;
+  const int kgrp = lane >> 4;
+
+  v4f acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = v4f{0, 0, 0, 0};
+  const int t_begin = rowptr[B], t_end = rowptr[B + 1];
+
+  // H staging: thread tid moves 8 consecutive bf16 of one tile row (16 bytes)
+  v8bf hreg;
+  auto load_h = [&](int t) {
+    hreg = *reinterpret_cast<const v8bf *>(vals + (int64_t)t * kTileElems + 8 * tid);
+  };
+  auto store_h = [&](int buf) {
+    const int r = tid >> 3, c8 = (tid & 7) * 8;          // row r, columns c8 .. c8+7
+    const int kk = c8 >> 5, g = (c8 & 31) >> 3, mb = r >> 4;
+    const int fl = (r & 15) + 16 * g;
+    *reinterpret_cast<v8bf *>(&sH[buf][((kk * 4 + mb) * 64 + fl) * 8]) = hreg;
+  };
+  // two register sets for the Y_k values: one being contracted, one being fetched
+  TX bA[2][8], bB[2][8];
+  auto load_b = [&](int t, TX (&dst)[2][8]) {
+    const TX *Xp = Yk + (int64_t)tcol[t] * 64 * ldk + col;
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int kr = 32 * kk + 8 * kgrp + q;
+        dst[kk][q] = col_ok ? Xp[(int64_t)kr * ldk] : TX(0);
+      }
+  };
+  // sub-blocks 4*kk4 + mb, kk4 = 8kk .. 8kk+7, sit at bits 32kk + 4j + mb
+  auto mma_tile = [&](int buf, uint64_t fm, const TX (&src)[2][8]) {
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      v8bf b;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) b[q] = (__bf16)to_f32<TX>(src[kk][q]);
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        if (((fm >> (32 * kk + mb)) & 0x11111111ull) == 0) continue;
+        const v8bf a = *reinterpret_cast<const v8bf *>(&sH[buf][((kk * 4 + mb) * 64 + lane) * 8]);
+        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[mb], 0, 0, 0);
+      }
+    }
+  };
+  auto step = [&](int t, int buf, const TX (&cur)[2][8], TX (&nxt)[2][8]) {
+    const bool more = t + 1 < t_end;
+    const uint64_t fm = frag_mask ? frag_mask[t] : ~0ull;
+    if (more) {
+      load_h(t + 1);
+      load_b(t + 1, nxt);
+    }
+    mma_tile(buf, fm, cur);
+    if (more) store_h(buf ^ 1);
+    __syncthreads();
+  };
+
+  if (t_begin < t_end) {
+    load_h(t_begin);
+    load_b(t_begin, bA);
+    store_h(0);
+    __syncthreads();
+  }
+  for (int t = t_begin; t < t_end; t += 2) {
+    step(t, 0, bA, bB);
+    if (t + 1 < t_end) step(t + 1, 1, bB, bA);
+  }
+
+  if (!col_ok) return;
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t grow = B * 64 + 16 * mb + 4 * (lane >> 4) + q;
+      const float y = to_f32<TX>(Yk[grow * ldk + col]);
+      float out = alpha * (acc[mb][q] - c * y);
+      if (beta != 0.0f) out -= beta * to_f32<TX>(Yp[grow * ldp + col]);
+      Yo[grow * ldo + col] = from_f32<TX>(out);
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, const void *Yp,
@@ -276,14 +386,23 @@ hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, con
                          ldk, (const float *)Yp, ldp, (float *)Yo, ldo, n_vec, ctp,
                          H.n_block_rows, cgroup, wg, (float)alpha, (float)c, (float)beta,
                          H.frag_mask);
-  } else if (xt == TTDFT_F32) {
-    hipLaunchKernelGGL(cheb_step_bf16<float>, grid, block, 0, s, H.tile_rowptr, H.tile_col,
-                       (const __bf16 *)H.vals, (const float *)Yk, ldk, (const float *)Yp, ldp,
-                       (float *)Yo, ldo, n_vec, n_ct, n_wg, (float)alpha, (float)c, (float)beta);
   } else {
-    hipLaunchKernelGGL(cheb_step_bf16<__bf16>, grid, block, 0, s, H.tile_rowptr, H.tile_col,
-                       (const __bf16 *)H.vals, (const __bf16 *)Yk, ldk, (const __bf16 *)Yp, ldp,
-                       (__bf16 *)Yo, ldo, n_vec, n_ct, n_wg, (float)alpha, (float)c, (float)beta);
+    const int64_t ctp = (n_vec + F64_NV - 1) / F64_NV;
+    const int64_t cgroup = std::min<int64_t>(ctp, 2);
+    const int64_t n_groups = (ctp + cgroup - 1) / cgroup;
+    const int64_t wg = n_groups * H.n_block_rows * cgroup;
+    if (wg > 0x7fffffff) return hipErrorInvalidConfiguration;
+    if (xt == TTDFT_F32)
+      hipLaunchKernelGGL(cheb_step_bf16_pipe<float>, dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
+                         H.tile_rowptr, H.tile_col, (const __bf16 *)H.vals, (const float *)Yk, ldk,
+                         (const float *)Yp, ldp, (float *)Yo, ldo, n_vec, ctp, H.n_block_rows,
+                         cgroup, wg, (float)alpha, (float)c, (float)beta, H.frag_mask);
+    else
+      hipLaunchKernelGGL(cheb_step_bf16_pipe<__bf16>, dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
+                         H.tile_rowptr, H.tile_col, (const __bf16 *)H.vals, (const __bf16 *)Yk,
+                         ldk, (const __bf16 *)Yp, ldp, (__bf16 *)Yo, ldo, n_vec, ctp,
+                         H.n_block_rows, cgroup, wg, (float)alpha, (float)c, (float)beta,
+                         H.frag_mask);
   }
   return hipGetLastError();
 }

@@ -55,14 +55,15 @@ __global__ void gram_scale_diag_kernel(const double *G, int64_t n, int64_t np, d
   }
 }
 
-// Gs = D^-1 G D^-1 on the n x n part, identity on the padding; X (the future
-// L^{-1}) cleared.
-__global__ void gram_scale_kernel(double *G, int64_t n, int64_t np, const double *d, double *X) {
+// Gs = D^-1 G D^-1 (+ shift on the diagonal) on the n x n part, identity on the
+// padding; X (the future L^{-1}) cleared.
+__global__ void gram_scale_kernel(double *G, int64_t n, int64_t np, const double *d, double *X,
+                                  double shift) {
   const int64_t total = np * np;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
     const int64_t i = e / np, j = e % np;
     double v;
-    if (i < n && j < n) v = G[e] / (d[i] * d[j]);
+    if (i < n && j < n) v = G[e] / (d[i] * d[j]) + (i == j ? shift : 0.0);
     else v = (i == j) ? 1.0 : 0.0;
     G[e] = v;
     X[e] = 0.0;
@@ -220,12 +221,12 @@ size_t chol_rinv_scratch_doubles(int64_t n) {
 
 // G: np x np (np = padded n, ld np) holding Y^T Y in its n x n part; Rinv: np x np.
 hipError_t launch_chol_rinv(double *G, int64_t n, double *Rinv, double *scratch, int *info,
-                            hipStream_t s) {
+                            hipStream_t s, double shift) {
   const int64_t np = (n + T - 1) / T * T;
   const int nb = (int)(np / T);
   double *X = scratch, *d = scratch + np * np;
   hipLaunchKernelGGL(gram_scale_diag_kernel, dim3(grid_for(np)), dim3(256), 0, s, G, n, np, d, info);
-  hipLaunchKernelGGL(gram_scale_kernel, dim3(grid_for(np * np)), dim3(256), 0, s, G, n, np, d, X);
+  hipLaunchKernelGGL(gram_scale_kernel, dim3(grid_for(np * np)), dim3(256), 0, s, G, n, np, d, X, shift);
   for (int p = 0; p < nb; ++p) {
     hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, G, np, p, X, info);
     if (p + 1 < nb) {

@@ -259,33 +259,53 @@ __global__ __launch_bounds__(256) void inverse_iteration_kernel(
 #undef AT
 }
 
-// Back-transformation by one reflector: Z[k+1:, :] -= tau v (v^T Z[k+1:, :]).
-// Pass 1: partial[y][c] = sum over rows 64y .. 64y+63 of v_i Z[i][c].
-__global__ __launch_bounds__(256) void backtr_partial_kernel(const double *A, int64_t n, int64_t k,
-                                                             const double *Z, int64_t ldz,
-                                                             double *partial) {
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (c >= n) return;
-  const int64_t m = n - k - 1, r0 = (int64_t)blockIdx.y * 64, r1 = min(m, r0 + 64);
-  const double *v = A + k * n + k + 1;
-  double s = 0.0;
-  for (int64_t i = r0; i < r1; ++i) s += v[i] * Z[(k + 1 + i) * ldz + c];
-  partial[(int64_t)blockIdx.y * n + c] = s;
+// Back-transformation in blocks of WY_NB reflectors (compact WY form):
+// H_k0 H_k0+1 ... H_k1-1 = I - V T V^T, V = [v_k0 .. v_k1-1], T upper triangular
+// with T_jj = tau_j and T[0:j, j] = -tau_j T[0:j, 0:j] (V[:, 0:j]^T v_j).
+constexpr int WY_NB = 64;
+
+// Vt row j = v_{k0+j} (zero at and above position k0+j, 1 at k0+j+1)
+__global__ __launch_bounds__(256) void wy_vrows_kernel(const double *A, int64_t n, int64_t k0,
+                                                       int nb, double *Vt) {
+  const int64_t total = (int64_t)nb * n;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t j = e / n, i = e % n, k = k0 + j;
+    Vt[e] = i > k ? A[k * n + i] : 0.0;
+  }
 }
 
-// Pass 2: w_c = sum_y partial[y][c] (fixed order), then the rows of chunk y.
-__global__ __launch_bounds__(256) void backtr_update_kernel(const double *A, int64_t n, int64_t k,
-                                                            const double *tau, double *Z,
-                                                            int64_t ldz, const double *partial) {
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (c >= n) return;
-  const int64_t m = n - k - 1, ny = (m + 63) / 64;
-  double w = 0.0;
-  for (int64_t y = 0; y < ny; ++y) w += partial[y * n + c];
-  const double tw = tau[k] * w;
-  const double *v = A + k * n + k + 1;
-  const int64_t r0 = (int64_t)blockIdx.y * 64, r1 = min(m, r0 + 64);
-  for (int64_t i = r0; i < r1; ++i) Z[(k + 1 + i) * ldz + c] -= v[i] * tw;
+// G[i][j] = v_i . v_j for i < j (one wave per pair)
+__global__ __launch_bounds__(256) void wy_gram_kernel(const double *Vt, int64_t n, int64_t k0,
+                                                      int nb, double *G) {
+  const int pair = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (pair >= nb * nb) return;
+  const int i = pair / nb, j = pair % nb;
+  if (i >= j) return;
+  double s = 0.0;
+  for (int64_t x = k0 + 1 + j + lane; x < n; x += 64) s += Vt[(int64_t)i * n + x] * Vt[(int64_t)j * n + x];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (lane == 0) G[i * nb + j] = s;
+}
+
+// T from G and tau (one work-group, nb <= 64)
+__global__ __launch_bounds__(64) void wy_t_kernel(const double *G, const double *tau, int64_t k0,
+                                                  int nb, double *T) {
+  const int i = threadIdx.x;
+  for (int j = 0; j < nb; ++j) {
+    if (i < nb) T[i * nb + j] = 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const double tj = tau[k0 + j];
+    double s = 0.0;
+    if (i < j) {
+      for (int l = i; l < j; ++l) s += T[i * nb + l] * G[l * nb + j];
+    }
+    __syncthreads();
+    if (i < j) T[i * nb + j] = -tj * s;
+    if (i == j) T[j * nb + j] = tj;
+    __syncthreads();
+  }
 }
 
 __global__ void clear_ints_kernel(int *p, int count) {
@@ -299,7 +319,7 @@ inline unsigned grid_for(int64_t work) {
 
 struct SyevLayout {
   int64_t n, np, splits;
-  size_t a, dg, du, du2, dl, swp, zt, z2, g, m, chol, partial, vec, info, total;
+  size_t a, dg, du, du2, dl, swp, zt, z2, g, m, chol, partial, vec, info, wy, total;
 };
 
 SyevLayout syev_layout(int64_t n) {
@@ -320,6 +340,7 @@ SyevLayout syev_layout(int64_t n) {
   L.partial = take((size_t)L.splits * nn);
   L.vec = take(8 * (size_t)n + 8);
   L.info = take(4);
+  L.wy = take(3 * (size_t)WY_NB * n + 2 * (size_t)WY_NB * WY_NB);
   L.total = off;
   return L;
 }
@@ -371,12 +392,28 @@ hipError_t run_syev(int64_t n, const double *Ain, int64_t lda, double *lambda, d
     if ((err = launch_chol_rinv(G, n, M, chol, info, s)) != hipSuccess) return err;
     if ((err = launch_gemm_nn_ex(src, n, M, L.np, n, n, n, 1.0, dst, n, true, s)) != hipSuccess) return err;
   }
-  // 5. back-transformation Z = H_0 ... H_{n-3} Zt
+  // 5. back-transformation Z = H_0 ... H_{n-3} Zt, blocks of reflectors from the last:
+  //    Z[k0+1:, :] -= V (T (V^T Z[k0+1:, :]))
   hipLaunchKernelGGL(copy_matrix_kernel, dim3(grid_for(n * n)), dim3(256), 0, s, Zt, n, Z, ldz, n);
-  for (int64_t k = n - 3; k >= 0; --k) {
-    const dim3 g((unsigned)((n + 255) / 256), (unsigned)((n - k - 1 + 63) / 64));
-    hipLaunchKernelGGL(backtr_partial_kernel, g, dim3(256), 0, s, A, n, k, Z, ldz, du);
-    hipLaunchKernelGGL(backtr_update_kernel, g, dim3(256), 0, s, A, n, k, tau, Z, ldz, du);
+  {
+    const int64_t R = n - 2;                        // reflectors k = 0 .. n-3
+    double *Vt = (double *)(w + L.wy), *W = Vt + (int64_t)WY_NB * n, *W2 = Vt + 2 * (int64_t)WY_NB * n;
+    double *Gw = Vt + 3 * (int64_t)WY_NB * n, *Tw = Gw + WY_NB * WY_NB;
+    for (int64_t k0 = (R > 0 ? (R - 1) / WY_NB * WY_NB : -1); k0 >= 0; k0 -= WY_NB) {
+      const int nb = (int)std::min<int64_t>(WY_NB, R - k0);
+      const int64_t m = n - k0 - 1;                 // rows touched
+      hipLaunchKernelGGL(wy_vrows_kernel, dim3(grid_for((int64_t)nb * n)), dim3(256), 0, s, A, n, k0, nb, Vt);
+      hipLaunchKernelGGL(wy_gram_kernel, dim3((unsigned)((nb * nb + 3) / 4)), dim3(256), 0, s, Vt, n, k0, nb, Gw);
+      hipLaunchKernelGGL(wy_t_kernel, dim3(1), dim3(64), 0, s, Gw, tau, k0, nb, Tw);
+      // W = V^T Z[k0+1:, :]   (nb x n)
+      if ((err = launch_gemm_nn_ex(Vt + k0 + 1, n, Z + (k0 + 1) * ldz, ldz, nb, m, n, 1.0, W, n,
+                                   false, s)) != hipSuccess) return err;
+      // W2 = T W
+      if ((err = launch_gemm_nn_ex(Tw, nb, W, n, nb, nb, n, 1.0, W2, n, false, s)) != hipSuccess) return err;
+      // Z[k0+1:, :] -= V W2
+      if ((err = launch_gemm_tn_acc(Vt + k0 + 1, n, W2, n, nb, m, n, -1.0, Z + (k0 + 1) * ldz, ldz, s)) != hipSuccess)
+        return err;
+    }
   }
   if ((err = hipGetLastError()) != hipSuccess) return err;
   if ((err = hipStreamSynchronize(s)) != hipSuccess) return err;

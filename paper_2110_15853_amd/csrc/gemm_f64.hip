@@ -209,7 +209,45 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_nn_kernel(
     }
 }
 
+// C[M x N] += alpha * A^T B with A: K x M (lda), B: K x N (ldb), small K (no split)
+__global__ __launch_bounds__(THREADS, 2) void gemm_tn_acc_kernel(
+    const double *__restrict__ A, int64_t lda, const double *__restrict__ B, int64_t ldb,
+    int64_t K, int64_t M, int64_t N, double alpha, double *__restrict__ C, int64_t ldc,
+    int tiles_n) {
+  __shared__ double sA[2][BK][LDS_LD];
+  __shared__ double sB[2][BK][LDS_LD];
+  const int64_t tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  const int64_t i0 = tm * BM, j0 = tn * BN;
+  Tile<true> T;
+  T.sA = sA;
+  T.sB = sB;
+  T.run(A, lda, B, ldb, i0, j0, 0, K, M, N);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t col = j0 + 64 * wn + 16 * j + (lane & 15);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t row = i0 + 64 * wm + 16 * i + out_row(lane, t);
+        if (row < M && col < N) C[row * ldc + col] += alpha * T.acc[i][j][t];
+      }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_gemm_tn_acc(const double *A, int64_t lda, const double *B, int64_t ldb,
+                              int64_t K, int64_t M, int64_t N, double alpha, double *C,
+                              int64_t ldc, hipStream_t s) {
+  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  const int tiles_n = (int)((N + BN - 1) / BN);
+  const int64_t g = ((M + BM - 1) / BM) * tiles_n;
+  hipLaunchKernelGGL(gemm_tn_acc_kernel, dim3((unsigned)g), dim3(THREADS), 0, s, A, lda, B, ldb, K,
+                     M, N, alpha, C, ldc, tiles_n);
+  return hipGetLastError();
+}
 
 int gemm_tn_splits(int64_t rows, int64_t n) {
   const int64_t tiles = ((n + BM - 1) / BM) * ((n + BM - 1) / BM);

@@ -69,27 +69,64 @@ QrLayout qr_layout(int64_t rows, int64_t n) {
   return L;
 }
 
-// Y (any dtype) -> Q (FP64) = Cholesky-QR applied twice.  Enqueues only.
-hipError_t cholqr2_enqueue(const void *Y, int64_t ldy, ttdft_dtype ydt, int64_t rows, int64_t n,
-                           double *Q, int64_t ldq, char *work, const QrLayout &L, hipStream_t s) {
-  double *W = (double *)(work + L.w), *G = (double *)(work + L.g), *M = (double *)(work + L.m);
+// one Cholesky-QR pass: dst = src D^{-1} R^{-1}, with D^{-1} G D^{-1} + shift I = R^T R
+hipError_t cholqr_pass(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
+                       int64_t n, double shift, char *work, const QrLayout &L, hipStream_t s) {
+  double *G = (double *)(work + L.g), *M = (double *)(work + L.m);
   double *chol = (double *)(work + L.chol), *partial = (double *)(work + L.partial);
   int *info = (int *)(work + L.info);
   hipError_t e;
-  if ((e = launch_clear_ints(info, 4, s)) != hipSuccess) return e;
-  const double *src = (const double *)Y;
-  int64_t lds = ldy;
-  if (ydt != TTDFT_F64) {  // precision cast: the orthonormalisation is FP64
-    if ((e = launch_cast(Y, ydt, ldy, Q, TTDFT_F64, ldq, rows, n, s)) != hipSuccess) return e;
-    src = Q;
-    lds = ldq;
-  }
   if ((e = launch_gemm_tn(src, lds, src, lds, rows, n, G, L.np, true, partial, L.splits, s))) return e;
-  if ((e = launch_chol_rinv(G, n, M, chol, info, s)) != hipSuccess) return e;
-  if ((e = launch_gemm_nn_ex(src, lds, M, L.np, rows, n, n, 1.0, W, n, true, s))) return e;
-  if ((e = launch_gemm_tn(W, n, W, n, rows, n, G, L.np, true, partial, L.splits, s))) return e;
-  if ((e = launch_chol_rinv(G, n, M, chol, info, s)) != hipSuccess) return e;
-  return launch_gemm_nn_ex(W, n, M, L.np, rows, n, n, 1.0, Q, ldq, true, s);
+  if ((e = launch_chol_rinv(G, n, M, chol, info, s, shift)) != hipSuccess) return e;
+  return launch_gemm_nn_ex(src, lds, M, L.np, rows, n, n, 1.0, dst, ldd, true, s);
+}
+
+// FP64 copy of Y into Q when Y is not FP64 (the orthonormalisation is FP64)
+const double *fp64_source(const void *Y, int64_t ldy, ttdft_dtype ydt, int64_t rows, int64_t n,
+                          double *Q, int64_t ldq, int64_t *lds, hipStream_t s, hipError_t *e) {
+  *e = hipSuccess;
+  if (ydt == TTDFT_F64) {
+    *lds = ldy;
+    return (const double *)Y;
+  }
+  *e = launch_cast(Y, ydt, ldy, Q, TTDFT_F64, ldq, rows, n, s);
+  *lds = ldq;
+  return Q;
+}
+
+// Y (any dtype) -> Q (FP64) = Cholesky-QR applied twice.  Enqueues only.
+hipError_t cholqr2_enqueue(const void *Y, int64_t ldy, ttdft_dtype ydt, int64_t rows, int64_t n,
+                           double *Q, int64_t ldq, char *work, const QrLayout &L, hipStream_t s) {
+  double *W = (double *)(work + L.w);
+  hipError_t e;
+  if ((e = launch_clear_ints((int *)(work + L.info), 4, s)) != hipSuccess) return e;
+  int64_t lds;
+  const double *src = fp64_source(Y, ldy, ydt, rows, n, Q, ldq, &lds, s, &e);
+  if (e != hipSuccess) return e;
+  if ((e = cholqr_pass(src, lds, W, n, rows, n, 0.0, work, L, s)) != hipSuccess) return e;
+  return cholqr_pass(W, n, Q, ldq, rows, n, 0.0, work, L, s);
+}
+
+// Shifted Cholesky-QR3 (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa): a
+// first pass with the diagonal shift s = 11 (rows n + n (n+1)) u ||Gs||, with
+// ||Gs|| <= n for the unit-diagonal scaled Gram matrix, makes the block well
+// enough conditioned for Cholesky-QR2.  Used after a breakdown of the plain
+// passes; needs Y intact (Q must not alias Y).
+hipError_t shifted_cholqr3_enqueue(const void *Y, int64_t ldy, ttdft_dtype ydt, int64_t rows,
+                                   int64_t n, double *Q, int64_t ldq, char *work, const QrLayout &L,
+                                   hipStream_t s) {
+  double *W = (double *)(work + L.w);
+  hipError_t e;
+  if ((e = launch_clear_ints((int *)(work + L.info), 4, s)) != hipSuccess) return e;
+  int64_t lds;
+  const double *src = fp64_source(Y, ldy, ydt, rows, n, Q, ldq, &lds, s, &e);
+  if (e != hipSuccess) return e;
+  const double u = 1.1102230246251565e-16;
+  const double shift = 11.0 * ((double)rows * n + (double)n * (n + 1)) * u * (double)n;
+  if ((e = cholqr_pass(src, lds, W, n, rows, n, shift, work, L, s)) != hipSuccess) return e;
+  if ((e = cholqr_pass(W, n, Q, ldq, rows, n, 0.0, work, L, s)) != hipSuccess) return e;
+  if ((e = cholqr_pass(Q, ldq, W, n, rows, n, 0.0, work, L, s)) != hipSuccess) return e;
+  return launch_cast(W, TTDFT_F64, n, Q, TTDFT_F64, ldq, rows, n, s);
 }
 
 ttdft_status check_h64(const ttdft_bsr *H) {
@@ -148,13 +185,31 @@ RrLayout rr_layout(int64_t rows, int64_t n) {
   return L;
 }
 
-ttdft_status finish_qr(char *work, const QrLayout &L, hipStream_t s) {
-  hipError_t e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(e, "cholqr2");
+// 0 when the enqueued passes succeeded, else the breakdown column (1-based)
+int qr_breakdown(char *work, const QrLayout &L, hipStream_t s, hipError_t *e) {
+  *e = hipStreamSynchronize(s);
+  if (*e != hipSuccess) return 0;
   int info[2] = {0, 0};
-  e = hipMemcpy(info, work + L.info, sizeof info, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(e, "cholqr2 info");
-  if (info[0]) return failf(TTDFT_ERR_NOT_POSDEF, "Cholesky breakdown at column %d: block rank-deficient in FP64", info[0]);
+  *e = hipMemcpy(info, work + L.info, sizeof info, hipMemcpyDeviceToHost);
+  return info[0];
+}
+
+// Cholesky-QR2, and shifted Cholesky-QR3 when the plain passes break down
+ttdft_status orthonormalise(const void *Y, int64_t ldy, ttdft_dtype ydt, int64_t rows, int64_t n,
+                            double *Q, int64_t ldq, char *work, const QrLayout &L, hipStream_t s,
+                            bool y_intact_after) {
+  hipError_t e = cholqr2_enqueue(Y, ldy, ydt, rows, n, Q, ldq, work, L, s);
+  if (e != hipSuccess) return hip_fail(e, "cholqr2 launch");
+  int col = qr_breakdown(work, L, s, &e);
+  if (e != hipSuccess) return hip_fail(e, "cholqr2");
+  if (col == 0) return TTDFT_OK;
+  if (!y_intact_after)
+    return failf(TTDFT_ERR_NOT_POSDEF, "Cholesky breakdown at column %d (Q aliases Y: no retry)", col);
+  e = shifted_cholqr3_enqueue(Y, ldy, ydt, rows, n, Q, ldq, work, L, s);
+  if (e != hipSuccess) return hip_fail(e, "shifted cholqr3 launch");
+  col = qr_breakdown(work, L, s, &e);
+  if (e != hipSuccess) return hip_fail(e, "shifted cholqr3");
+  if (col) return failf(TTDFT_ERR_NOT_POSDEF, "Cholesky breakdown at column %d: block rank-deficient in FP64", col);
   return TTDFT_OK;
 }
 
@@ -183,9 +238,8 @@ ttdft_status ttdft_cholqr2(const void *Y, int64_t ldy, ttdft_dtype y_dtype, int6
   if (overlap(work, L.total, Q, qb) || overlap(work, L.total, Y, yb))
     return failf(TTDFT_ERR_ALIAS, "workspace overlaps Y or Q");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = cholqr2_enqueue(Y, ldy, y_dtype, n_rows, n_vec, Q, ldq, (char *)work, L, s);
-  if (e != hipSuccess) return hip_fail(e, "cholqr2 launch");
-  ttdft_status st = finish_qr((char *)work, L, s);
+  const bool intact = (const void *)Y != (const void *)Q;
+  ttdft_status st = orthonormalise(Y, ldy, y_dtype, n_rows, n_vec, Q, ldq, (char *)work, L, s, intact);
   return st == TTDFT_OK ? api_ok() : st;
 }
 
@@ -269,11 +323,9 @@ ttdft_status ttdft_rayleigh_ritz(const ttdft_bsr *H, const void *Y, int64_t ldy,
   char *w = (char *)work;
   hipStream_t s = (hipStream_t)stream;
   double *XF = (double *)(w + L.xf), *Hf = (double *)(w + L.hf), *Zq = (double *)(w + L.zq);
-  hipError_t e = cholqr2_enqueue(Y, ldy, y_dtype, rows, n_vec, XF, n_vec, w + L.qr_off, L.qr, s);
-  if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: cholqr2");
-  st = finish_qr(w + L.qr_off, L.qr, s);
+  st = orthonormalise(Y, ldy, y_dtype, rows, n_vec, XF, n_vec, w + L.qr_off, L.qr, s, true);
   if (st != TTDFT_OK) return st;
-  e = project_enqueue(*H, XF, n_vec, n_vec, Hf, n_vec, w + L.pj_off, L.pj, s);
+  hipError_t e = project_enqueue(*H, XF, n_vec, n_vec, Hf, n_vec, w + L.pj_off, L.pj, s);
   if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: projection");
   int info[2] = {0, 0};
   e = run_syev(n_vec, Hf, n_vec, lambda, Zq, n_vec, w + L.syev, s, info);

@@ -55,13 +55,17 @@ hipError_t launch_gemm_nn_ex(const double *A, int64_t lda, const double *B, int6
                              int64_t rows, int64_t K, int64_t N, double alpha, double *C,
                              int64_t ldc, bool upper, hipStream_t s);
 hipError_t launch_clear_ints(int *p, int count, hipStream_t s);
+// C[M x N] += alpha * A^T B, A: K x M, B: K x N (small K, no split)
+hipError_t launch_gemm_tn_acc(const double *A, int64_t lda, const double *B, int64_t ldb,
+                              int64_t K, int64_t M, int64_t N, double alpha, double *C,
+                              int64_t ldc, hipStream_t s);
 
 // ---- small dense FP64 factorisations (device)
-// In-place scaled Cholesky-QR core: given G (n x n, ld n) = Y^T Y, forms
-// D = diag(G)^{1/2}, Gs = D^-1 G D^-1, Gs = R^T R, and writes Rinv = D^-1 R^-1 (upper).
-// info (device int) is set non-zero on breakdown.
+// In-place scaled Cholesky-QR core: given G (np x np, ld np) with Y^T Y in its
+// n x n part, forms D = diag(G)^{1/2}, Gs = D^-1 G D^-1 + shift*I, Gs = R^T R, and
+// writes Rinv = D^-1 R^-1 (upper).  info (device int) is set non-zero on breakdown.
 hipError_t launch_chol_rinv(double *G, int64_t n, double *Rinv, double *scratch, int *info,
-                            hipStream_t s);
+                            hipStream_t s, double shift = 0.0);
 size_t chol_rinv_scratch_doubles(int64_t n);
 
 hipError_t launch_symmetrize(double *A, int64_t n, int64_t lda, hipStream_t s);

@@ -46,10 +46,26 @@ def test_cholqr2_reports_breakdown():
     torch, P = require_gpu()
     rng = np.random.default_rng(8)
     Y = rng.standard_normal((500, 20))
-    Y[:, 7] = Y[:, 3]                                  # rank-deficient
+    Y[:, 7] = 0.0                                      # rank-deficient: no orthonormal Q spans Y
     with pytest.raises(P.TtdftError) as ei:
         P.cholqr2(_cuda(Y))
     assert ei.value.name == "TTDFT_ERR_NOT_POSDEF"
+
+
+@pytest.mark.parametrize("ydtype", ["f64", "f32"])
+def test_shifted_cholqr3_fallback_ill_conditioned(ydtype):
+    # singular values down to 1e-12: the Gram matrix is singular to working
+    # precision, the plain passes break down and the shifted pass takes over
+    torch, P = require_gpu()
+    rng = np.random.default_rng(9)
+    U, _ = np.linalg.qr(rng.standard_normal((3000, 60)))
+    V, _ = np.linalg.qr(rng.standard_normal((60, 60)))
+    Y = (U * np.logspace(0, -12, 60)) @ V.T
+    Yd = _cuda(Y) if ydtype == "f64" else _cuda(Y).float()
+    Yh = Yd.double().cpu().numpy()
+    Q = P.cholqr2(Yd).cpu().numpy()
+    assert np.max(np.abs(Q.T @ Q - np.eye(60))) <= 1e-13
+    assert np.linalg.norm(Yh - Q @ (Q.T @ Yh)) <= 1e-12 * np.linalg.norm(Yh)
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 37, 200, 513])

@@ -90,11 +90,14 @@ def lattice_hamiltonian(r: int, h: int, seed: int = 0):
     return indptr, indices, data, N
 
 
-def gaussian_block(N: int, n: int, seed: int = 0, stream: str = "X") -> np.ndarray:
-    """N x n float64 block of N(0,1) draws, row-major, from the X or W stream."""
+def gaussian_block(N: int, n: int, seed: int = 0, stream: str = "X",
+                   dtype=np.float64) -> np.ndarray:
+    """N x n block of N(0,1) draws, row-major, from the X or W stream.
+    dtype float32 draws single-precision normals directly (a different, equally
+    seeded sequence; used where the block is held in FP32)."""
     _, rng_x, rng_w = stream_rngs(seed)
     rng = {"X": rng_x, "W": rng_w}[stream]
-    return rng.standard_normal((N, n))
+    return rng.standard_normal((N, n), dtype=dtype)
 
 
 @dataclass(frozen=True)
@@ -124,6 +127,8 @@ CONFIGS = {
     "lattice40_h3_n512_m16": WorkloadConfig("lattice40_h3_n512_m16", r=40, h=3, n=512, m=16),
     # dense-reference adjoint case (lattice not a multiple of 4)
     "lattice10_h3_n16_m16": WorkloadConfig("lattice10_h3_n16_m16", r=10, h=3, n=16, m=16),
-    # large mixed-precision step
+    # large mixed-precision step (X held in FP32)
     "lattice90_h3_n8000_m24": WorkloadConfig("lattice90_h3_n8000_m24", r=90, h=3, n=8000, m=24),
+    # reduced version of the large step for quick checks (same lattice stencil and degree)
+    "lattice30_h3_n512_m24": WorkloadConfig("lattice30_h3_n512_m24", r=30, h=3, n=512, m=24),
 }
