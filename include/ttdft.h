@@ -247,6 +247,28 @@ ttdft_status ttdft_rayleigh_ritz(const ttdft_bsr *H, const void *Y, int64_t ldy,
                                  double *Psi, int64_t ldpsi, void *work, size_t work_bytes,
                                  void *stream);
 
+/* ---------------------------------------------------------------- spectrum bound for [a, b] */
+
+/* Bytes of workspace ttdft_lanczos_upper_bound needs for k steps. */
+size_t ttdft_lanczos_workspace(const ttdft_bsr *H, int32_t k);
+
+/*
+ * Estimate of the upper end of the spectrum of H, for the upper bound b of the
+ * unwanted interval of the Chebyshev filter (Sec. 3.4): k steps of the Lanczos
+ * process from a seeded random start vector (zero on padding rows):
+ *   bound[0] = theta_max, the largest eigenvalue of the k x k Lanczos tridiagonal
+ *              (a lower estimate of the top of the spectrum),
+ *   bound[1] = theta_max + |beta_{k+1} s_k|, s_k the last component of its
+ *              eigenvector (theta_max plus its Ritz residual: the usual estimate),
+ *   bound[2] = theta_max + beta_{k+1} (safeguarded, pessimistic).
+ * H must be FP64.  perm: device int64 [64*n_block_rows] from ttdft_bsr_build
+ * (padding rows marked -1).  bound: host double[3].  Synchronises the stream.
+ * Errors: NULL, SHAPE (k outside 1..1000), DTYPE, WORKSPACE, NONFINITE, HIP.
+ */
+ttdft_status ttdft_lanczos_upper_bound(const ttdft_bsr *H, const int64_t *perm, int32_t k,
+                                       uint64_t seed, double *bound, void *work,
+                                       size_t work_bytes, void *stream);
+
 /* ---------------------------------------------------------------- adjoint of step 1 */
 
 /*

@@ -22,6 +22,7 @@ from .api import (  # noqa: F401
     cheb_filter_autograd,
     cheb_filter_backward,
     cholqr2,
+    lanczos_upper_bound,
     gather_rows,
     project,
     rayleigh_ritz,

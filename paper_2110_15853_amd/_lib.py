@@ -58,6 +58,8 @@ SIGNATURES = {
     "ttdft_cheb_filter_backward_workspace": (_SZ, [_BSRP, _I64, _I32, _I32, _INT]),
     "ttdft_cheb_filter_backward": (_INT, [_BSRP, _P, _I64, _P, _I64, _I64, _I32, _D, _D, _D, _INT,
                                           _I32, _P, _I64, _P, _P, _P, _SZ, _P]),
+    "ttdft_lanczos_workspace": (_SZ, [_BSRP, _I32]),
+    "ttdft_lanczos_upper_bound": (_INT, [_BSRP, _P, _I32, C.c_uint64, _P, _P, _SZ, _P]),
     "ttdft_status_string": (C.c_char_p, [_INT]),
     "ttdft_last_error": (C.c_char_p, []),
     "ttdft_version": (C.c_char_p, []),

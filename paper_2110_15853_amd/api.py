@@ -307,3 +307,14 @@ def updated_bounds(lam: torch.Tensor, b: float):
     if not (lo < hi < b):
         raise ValueError("Ritz values do not leave a0 < a < b")
     return lo, hi
+
+
+def lanczos_upper_bound(H: BsrMatrix, k: int = 20, seed: int = 0):
+    """ttdft_lanczos_upper_bound: (theta_max, theta_max + Ritz residual,
+    theta_max + beta_{k+1}) for an FP64 H."""
+    hs = H.c_struct()
+    out = (C.c_double * 3)()
+    w = _work(_lib.load().ttdft_lanczos_workspace(C.byref(hs), k), H.vals.device)
+    _lib.call("ttdft_lanczos_upper_bound", C.byref(hs), _ptr(H.perm), k, seed, out, _ptr(w),
+              w.numel(), _stream())
+    return float(out[0]), float(out[1]), float(out[2])

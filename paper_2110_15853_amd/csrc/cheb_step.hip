@@ -22,17 +22,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-constexpr int NV = 64;        // vectors per work-group
-constexpr int THREADS = 256;  // 4 waves
 
-// Work-groups are dispatched round-robin over the 8 XCDs.  Remap the hardware
-// id so each XCD gets a contiguous range of logical ids: consecutive logical ids
-// share a block row (and so its H tiles) inside one XCD's L2.
-__device__ inline int64_t xcd_remap(int64_t g, int64_t G) {
-  const int64_t xcd = g % 8, local = g / 8;
-  const int64_t per = G / 8, rem = G % 8;
-  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
-}
 
 // MFMA 16x16x4 on scalar operands: lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // output item t of lane l is D[row(l, t)][l%16].
@@ -55,12 +45,23 @@ template <> struct Mfma4<float> {
 // Pipelined FP64 / FP32 path.  8 waves per work-group; the work-group owns block row B and
 // 128 vectors, wave w the 64 x 16 output slab of vectors 16w .. 16w+15.
 //  - A operand (H tile): double-buffered in LDS in matrix-core fragment order,
-//    element H[16*mb + (l & 15)][4*kk + (l >> 4)] at sH[buf][kk][mb][l], so each
-//    fragment read is 64 consecutive doubles; the next tile is fetched into
-//    registers while the current one is contracted (one barrier per tile).
+//    element H[16*mb + (l & 15)][4*kk + (l >> 4)] of fragment (kk, mb) in its
+//    64-slot region (lanes rotated within groups of 16, see store_h); the next
+//    tile is fetched into registers while the current one is contracted (one
+//    barrier per tile).
 //  - B operand (Y_k panel): each wave reads its own 16 vectors straight from
 //    global memory into registers, half a tile (8 k-steps) ahead of use.
 constexpr int F64_NV = 128, F64_THREADS = 512, F64_S = 65;   // fragment row stride (+1 pad)
+// launch order: column groups of ORDER_CGROUP tiles outermost; each XCD takes runs
+// of ORDER_CHUNK consecutive block rows (all column tiles of the group), the 8
+// XCDs working on neighbouring runs at the same time
+constexpr int ORDER_CGROUP = 16, ORDER_CHUNK = 1;
+// column blocks of 16 vectors per wave in the FP64 / FP32 kernel
+constexpr int PIPE_CB_F64 = 1, PIPE_CB_F32 = 1;
+// prefetch the next tile's Y_k fragments a whole tile ahead (else one quarter)
+constexpr bool PIPE_DEEP = true;
+// waves per SIMD the kernel is compiled for (register budget 512 / waves)
+template <typename T, int CB> constexpr int pipe_waves() { return (sizeof(T) == 8 && CB > 1) ? 2 : 4; }
 
 __device__ inline int64_t group_order(int64_t g, int64_t G, int64_t C) {
   // hardware ids go round-robin over 8 XCDs; give each XCD C consecutive logical
@@ -71,17 +72,20 @@ __device__ inline int64_t group_order(int64_t g, int64_t G, int64_t C) {
   return (g / span) * span + (g % 8) * C + (g / 8) % C;
 }
 
-// T = double (f64 16x16x4) or float (f32 16x16x4, same operand layouts)
-template <typename T>
-__global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_pipe(
+// T = double (f64 16x16x4) or float (f32 16x16x4, same operand layouts).
+// CB = column blocks of 16 vectors per wave: the work-group covers 8*16*CB
+// vectors and each A fragment read from LDS feeds CB matrix-core ops.
+template <typename T, int CB>
+__global__ __launch_bounds__(F64_THREADS, (pipe_waves<T, CB>())) void cheb_step_pipe(
     const int32_t *__restrict__ rowptr, const int32_t *__restrict__ tcol,
     const T *__restrict__ vals, const T *__restrict__ Yk, int64_t ldk,
     const T *__restrict__ Yp, int64_t ldp, T *Yo, int64_t ldo, int64_t n_vec,
     int64_t n_ct, int64_t n_block_rows, int64_t cgroup, int64_t n_wg, T alpha, T c,
     T beta, const uint64_t *__restrict__ frag_mask) {
   using M = Mfma4<T>;
+  constexpr int NVW = 16 * CB;            // vectors per wave
   __shared__ T sH[2][16 * 4 * F64_S];
-  const int64_t L = group_order(blockIdx.x, n_wg, cgroup);
+  const int64_t L = group_order(blockIdx.x, n_wg, cgroup * ORDER_CHUNK);
   // logical id -> (column group, block row, column tile inside the group)
   const int64_t per_group = n_block_rows * cgroup;
   const int64_t cg = L / per_group, rem = L % per_group;
@@ -89,16 +93,17 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_pipe(
   const int64_t ct = cg * cgroup + rem % cgroup;
   if (ct >= n_ct) return;        // last group may be partial (whole work-group exits)
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t col = ct * F64_NV + 16 * w + (lane & 15);
-  const bool col_ok = col < n_vec;
+  const int64_t col0 = ct * (8 * NVW) + NVW * w + (lane & 15);   // column of block cb: col0 + 16 cb
   const int krow = lane >> 4;    // row of the 4-row k-step this lane loads
 
-  typename M::acc_t acc[4];
+  typename M::acc_t acc[CB][4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = typename M::acc_t{0, 0, 0, 0};
+  for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[cb][j] = typename M::acc_t{0, 0, 0, 0};
 
   const int t_begin = rowptr[B], t_end = rowptr[B + 1];
-  T hreg[4], b0[4], b1[4];
+  T hreg[4], b0[CB][4], b1[CB][4];
 
   // next H tile: half h (rows 32h .. 32h+31) into registers, then into LDS
   auto load_h = [&](int t, int h) {
@@ -106,149 +111,136 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_pipe(
 #pragma unroll
     for (int q = 0; q < 4; ++q) hreg[q] = Ht[tid + F64_THREADS * q];
   };
+  // Fragment lane l = i + 16j lives at slot 16j + ((i + j) mod 16) of its
+  // fragment: with the fragment stride of 65 this makes both the row-wise stores
+  // below and the fragment reads free of LDS bank conflicts.
   auto store_h = [&](int buf, int h) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int idx = 2048 * h + tid + F64_THREADS * q, r = idx >> 6, cc = idx & 63;
-      const int kk = cc >> 2, mb = r >> 4, fl = (r & 15) + 16 * (cc & 3);
-      sH[buf][(kk * 4 + mb) * F64_S + fl] = hreg[q];
+      const int kk = cc >> 2, mb = r >> 4, j = cc & 3;
+      const int slot = 16 * j + (((r & 15) + j) & 15);
+      sH[buf][(kk * 4 + mb) * F64_S + slot] = hreg[q];
     }
   };
+  const int rd_slot = (lane & 48) + (((lane & 15) + (lane >> 4)) & 15);
   // quarter qq (k-steps 4qq .. 4qq+3, panel rows 16qq .. 16qq+15) of the Y_k panel of tile t
-  auto load_b = [&](int t, int qq, T (&dst)[4]) {
-    const T *Xp = Yk + ((int64_t)tcol[t] * 64 + 16 * qq + krow) * ldk + col;
+  auto load_b = [&](int t, int qq, T (&dst)[CB][4]) {
+    const T *Xp = Yk + ((int64_t)tcol[t] * 64 + 16 * qq + krow) * ldk + col0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) dst[q] = col_ok ? Xp[(int64_t)(4 * q) * ldk] : T(0);
+    for (int cb = 0; cb < CB; ++cb) {
+      const bool ok = col0 + 16 * cb < n_vec;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dst[cb][q] = ok ? Xp[(int64_t)(4 * q) * ldk + 16 * cb] : T(0);
+    }
   };
   // all-zero 16x4 sub-blocks of the tile (bit clear in fm) are skipped; fm is
   // uniform over the work-group, so the branch costs no divergence
-  auto mma_quarter = [&](const T *sA, int qq, const T (&bq)[4], uint64_t fm) {
+  auto mma_quarter = [&](const T *sA, int qq, const T (&bq)[CB][4], uint64_t fm) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int kk = 4 * qq + q;
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb)
-        if ((fm >> (kk * 4 + mb)) & 1ull)
-          acc[mb] = M::op(sA[(kk * 4 + mb) * F64_S + lane], bq[q], acc[mb]);
+        if ((fm >> (kk * 4 + mb)) & 1ull) {
+          const T a = sA[(kk * 4 + mb) * F64_S + rd_slot];
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) acc[cb][mb] = M::op(a, bq[cb][q], acc[cb][mb]);
+        }
     }
   };
 
+  if constexpr (PIPE_DEEP) {
+    // whole-tile prefetch: quarters 0..3 of tile t+1 are fetched while tile t is contracted
+    T b2[CB][4], b3[CB][4];
+    if (t_begin < t_end) {
+      load_b(t_begin, 0, b0);
+      load_b(t_begin, 1, b1);
+      load_b(t_begin, 2, b2);
+      load_b(t_begin, 3, b3);
+      load_h(t_begin, 0);
+      store_h(0, 0);
+      load_h(t_begin, 1);
+      store_h(0, 1);
+      __syncthreads();
+    }
+    int buf = 0;
+    for (int t = t_begin; t < t_end; ++t) {
+      const bool more = t + 1 < t_end;
+      const T *sA = sH[buf];
+      const uint64_t fm = frag_mask ? frag_mask[t] : ~0ull;
+      if (more) load_h(t + 1, 0);
+      mma_quarter(sA, 0, b0, fm);
+      if (more) load_b(t + 1, 0, b0);
+      if (more) store_h(buf ^ 1, 0);
+      mma_quarter(sA, 1, b1, fm);
+      if (more) load_b(t + 1, 1, b1);
+      if (more) load_h(t + 1, 1);
+      mma_quarter(sA, 2, b2, fm);
+      if (more) load_b(t + 1, 2, b2);
+      if (more) store_h(buf ^ 1, 1);
+      mma_quarter(sA, 3, b3, fm);
+      if (more) load_b(t + 1, 3, b3);
+      __syncthreads();
+      buf ^= 1;
+    }
+  } else {
   if (t_begin < t_end) {
-    load_b(t_begin, 0, b0);
-    load_b(t_begin, 1, b1);
-    load_h(t_begin, 0);
-    store_h(0, 0);
-    load_h(t_begin, 1);
-    store_h(0, 1);
-    __syncthreads();
-  }
-  int buf = 0;
-  for (int t = t_begin; t < t_end; ++t) {
-    const bool more = t + 1 < t_end;
-    const T *sA = sH[buf];
-    const uint64_t fm = frag_mask ? frag_mask[t] : ~0ull;
-    if (more) load_h(t + 1, 0);
-    mma_quarter(sA, 0, b0, fm);
-    load_b(t, 2, b0);
-    if (more) store_h(buf ^ 1, 0);
-    mma_quarter(sA, 1, b1, fm);
-    load_b(t, 3, b1);
-    if (more) load_h(t + 1, 1);
-    mma_quarter(sA, 2, b0, fm);
-    if (more) load_b(t + 1, 0, b0);
-    if (more) store_h(buf ^ 1, 1);
-    mma_quarter(sA, 3, b1, fm);
-    if (more) load_b(t + 1, 1, b1);
-    __syncthreads();
-    buf ^= 1;
+      load_b(t_begin, 0, b0);
+      load_b(t_begin, 1, b1);
+      load_h(t_begin, 0);
+      store_h(0, 0);
+      load_h(t_begin, 1);
+      store_h(0, 1);
+      __syncthreads();
+    }
+    int buf = 0;
+    for (int t = t_begin; t < t_end; ++t) {
+      const bool more = t + 1 < t_end;
+      const T *sA = sH[buf];
+      const uint64_t fm = frag_mask ? frag_mask[t] : ~0ull;
+      if (more) load_h(t + 1, 0);
+      mma_quarter(sA, 0, b0, fm);
+      load_b(t, 2, b0);
+      if (more) store_h(buf ^ 1, 0);
+      mma_quarter(sA, 1, b1, fm);
+      load_b(t, 3, b1);
+      if (more) load_h(t + 1, 1);
+      mma_quarter(sA, 2, b0, fm);
+      if (more) load_b(t + 1, 0, b0);
+      if (more) store_h(buf ^ 1, 1);
+      mma_quarter(sA, 3, b1, fm);
+      if (more) load_b(t + 1, 1, b1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  
   }
 
-  if (!col_ok) return;
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb) {
+  for (int cb = 0; cb < CB; ++cb) {
+    const int64_t col = col0 + 16 * cb;
+    if (col >= n_vec) continue;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t grow = B * 64 + 16 * mb + M::row(lane, q);
-      const T y = Yk[grow * ldk + col];
-      T out = alpha * (acc[mb][q] - c * y);
-      if (beta != T(0)) out -= beta * Yp[grow * ldp + col];
-      Yo[grow * ldo + col] = out;
+    for (int mb = 0; mb < 4; ++mb) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t grow = B * 64 + 16 * mb + M::row(lane, q);
+        const T y = Yk[grow * ldk + col];
+        T out = alpha * (acc[cb][mb][q] - c * y);
+        if (beta != T(0)) out -= beta * Yp[grow * ldp + col];
+        Yo[grow * ldo + col] = out;
+      }
     }
   }
 }
 
-// BF16 H tiles with FP32 or BF16 iterates; FP32 accumulation on the
-// 16x16x32 bf16 matrix op.  Lane l supplies A[l%16][8*(l/16) .. +7] and
-// B[8*(l/16) .. +7][l%16]; output item t is D[4*(l/16)+t][l%16].
 template <typename TX> __device__ inline float to_f32(TX v);
 template <> __device__ inline float to_f32<float>(float v) { return v; }
 template <> __device__ inline float to_f32<__bf16>(__bf16 v) { return (float)v; }
 template <typename TX> __device__ inline TX from_f32(float v);
 template <> __device__ inline float from_f32<float>(float v) { return v; }
 template <> __device__ inline __bf16 from_f32<__bf16>(float v) { return (__bf16)v; }
-
-template <typename TX>
-__global__ __launch_bounds__(THREADS) void cheb_step_bf16(
-    const int32_t *__restrict__ rowptr, const int32_t *__restrict__ tcol,
-    const __bf16 *__restrict__ vals, const TX *__restrict__ Yk, int64_t ldk,
-    const TX *__restrict__ Yp, int64_t ldp, TX *Yo, int64_t ldo, int64_t n_vec, int64_t n_ct,
-    int64_t n_wg, float alpha, float c, float beta) {
-  // rows padded by 8 bf16 (16 bytes) to spread LDS banks, keeping 16-byte alignment
-  __shared__ __attribute__((aligned(16))) __bf16 sH[64][64 + 8];
-  __shared__ __attribute__((aligned(16))) __bf16 sXT[NV][64 + 8];  // transposed panel: [vector][k]
-
-  const int64_t g = xcd_remap(blockIdx.x, n_wg);
-  const int64_t B = g / n_ct, ct = g % n_ct;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t col0 = ct * NV;
-
-  v4f acc[4];
-  for (int j = 0; j < 4; ++j) acc[j] = v4f{0, 0, 0, 0};
-
-  const int t_begin = rowptr[B], t_end = rowptr[B + 1];
-  for (int t = t_begin; t < t_end; ++t) {
-    const int64_t Bc = tcol[t];
-    const __bf16 *Ht = vals + (int64_t)t * kTileElems;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = tid + THREADS * q;
-      sH[idx >> 6][idx & 63] = Ht[idx];
-    }
-    const TX *Xp = Yk + Bc * 64 * ldk;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int idx = tid + THREADS * q;
-      const int r = idx >> 6, cc = idx & 63;
-      const int64_t col = col0 + cc;
-      sXT[cc][r] = col < n_vec ? (__bf16)to_f32<TX>(Xp[(int64_t)r * ldk + col]) : (__bf16)0.0f;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 64; kk += 32) {
-      const v8bf a = *reinterpret_cast<const v8bf *>(&sH[16 * w + (lane & 15)][kk + 8 * (lane >> 4)]);
-#pragma unroll
-      for (int jb = 0; jb < 4; ++jb) {
-        const v8bf b = *reinterpret_cast<const v8bf *>(&sXT[16 * jb + (lane & 15)][kk + 8 * (lane >> 4)]);
-        acc[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[jb], 0, 0, 0);
-      }
-    }
-    __syncthreads();
-  }
-
-#pragma unroll
-  for (int jb = 0; jb < 4; ++jb) {
-    const int64_t col = col0 + 16 * jb + (lane & 15);
-    if (col >= n_vec) continue;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int64_t grow = B * 64 + 16 * w + 4 * (lane >> 4) + t;
-      const float y = to_f32<TX>(Yk[grow * ldk + col]);
-      float out = alpha * (acc[jb][t] - c * y);
-      if (beta != 0.0f) out -= beta * to_f32<TX>(Yp[grow * ldp + col]);
-      Yo[grow * ldo + col] = from_f32<TX>(out);
-    }
-  }
-}
 
 // Pipelined BF16 path: BF16 H tiles, FP32 or BF16 iterates, FP32 accumulation
 // on the 16x16x32 bf16 op.  Same decomposition as cheb_step_pipe (8 waves,
@@ -269,7 +261,7 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_bf16_pipe(
     int64_t n_block_rows, int64_t cgroup, int64_t n_wg, float alpha, float c, float beta,
     const uint64_t *__restrict__ frag_mask) {
   __shared__ __attribute__((aligned(16))) __bf16 sH[2][2 * 4 * 64 * 8];   // [buf][kk][mb][lane][8]
-  const int64_t L = group_order(blockIdx.x, n_wg, cgroup);
+  const int64_t L = group_order(blockIdx.x, n_wg, cgroup * ORDER_CHUNK);
   const int64_t per_group = n_block_rows * cgroup;
   const int64_t cg = L / per_group, rem = L % per_group;
   const int64_t B = rem / cgroup;
@@ -365,30 +357,27 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_bf16_pipe(
 hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, const void *Yp,
                             int64_t ldp, void *Yo, int64_t ldo, int64_t n_vec, double alpha,
                             double c, double beta, ttdft_dtype xt, hipStream_t s) {
-  const int64_t n_ct = (n_vec + NV - 1) / NV;
-  const int64_t n_wg = H.n_block_rows * n_ct;
-  if (n_wg > 0x7fffffff) return hipErrorInvalidConfiguration;
-  const dim3 grid((unsigned)n_wg), block(THREADS);
   if (H.dtype == TTDFT_F64 || H.dtype == TTDFT_F32) {
-    const int64_t ctp = (n_vec + F64_NV - 1) / F64_NV;
-    const int64_t cgroup = std::min<int64_t>(ctp, 2);
+    const int cb = H.dtype == TTDFT_F64 ? PIPE_CB_F64 : PIPE_CB_F32;
+    const int64_t ctp = (n_vec + 128 * cb - 1) / (128 * cb);
+    const int64_t cgroup = std::min<int64_t>(ctp, ORDER_CGROUP);
     const int64_t n_groups = (ctp + cgroup - 1) / cgroup;
     const int64_t wg = n_groups * H.n_block_rows * cgroup;
     if (wg > 0x7fffffff) return hipErrorInvalidConfiguration;
     if (H.dtype == TTDFT_F64)
-      hipLaunchKernelGGL(cheb_step_pipe<double>, dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
-                         H.tile_rowptr, H.tile_col, (const double *)H.vals, (const double *)Yk,
+      hipLaunchKernelGGL((cheb_step_pipe<double, PIPE_CB_F64>), dim3((unsigned)wg), dim3(F64_THREADS),
+                         0, s, H.tile_rowptr, H.tile_col, (const double *)H.vals, (const double *)Yk,
                          ldk, (const double *)Yp, ldp, (double *)Yo, ldo, n_vec, ctp,
                          H.n_block_rows, cgroup, wg, alpha, c, beta, H.frag_mask);
     else
-      hipLaunchKernelGGL(cheb_step_pipe<float>, dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
-                         H.tile_rowptr, H.tile_col, (const float *)H.vals, (const float *)Yk,
+      hipLaunchKernelGGL((cheb_step_pipe<float, PIPE_CB_F32>), dim3((unsigned)wg), dim3(F64_THREADS),
+                         0, s, H.tile_rowptr, H.tile_col, (const float *)H.vals, (const float *)Yk,
                          ldk, (const float *)Yp, ldp, (float *)Yo, ldo, n_vec, ctp,
                          H.n_block_rows, cgroup, wg, (float)alpha, (float)c, (float)beta,
                          H.frag_mask);
   } else {
     const int64_t ctp = (n_vec + F64_NV - 1) / F64_NV;
-    const int64_t cgroup = std::min<int64_t>(ctp, 2);
+    const int64_t cgroup = std::min<int64_t>(ctp, ORDER_CGROUP);
     const int64_t n_groups = (ctp + cgroup - 1) / cgroup;
     const int64_t wg = n_groups * H.n_block_rows * cgroup;
     if (wg > 0x7fffffff) return hipErrorInvalidConfiguration;

@@ -45,80 +45,86 @@ __global__ void copy_matrix_kernel(const double *A, int64_t lda, double *B, int6
   }
 }
 
-// Householder reflector for row k (x = A[k][k+1:n]); v (v0 = 1) overwrites
-// A[k][k+1:n]; d[k] = A[k][k], e[k] = beta, tau[k].
-__global__ __launch_bounds__(1024) void house_kernel(double *A, int64_t n, int64_t k, double *tau,
-                                                     double *d, double *e, int *nonfinite) {
-  __shared__ double red[1024 / 64 + 1];
-  double *x = A + k * n + k + 1;
-  const int64_t m = n - k - 1;
+// Householder reflector of row k, x = A[k][k+1:n]: beta = -sign(x0) |x|,
+// tau = (beta - x0)/beta, v = x/(x0 - beta) with v0 = 1 (tau = 0 when x1: = 0).
+// Every work-group of the product kernel computes it from the unmodified row;
+// work-group 0 stores v (row k of V), tau, d[k] and e[k].
+__device__ inline void reflector(const double *x, int64_t m, double *red, double &tau_k,
+                                 double &scale, double &beta) {
   double s = 0.0;
-  for (int64_t i = 1 + threadIdx.x; i < m; i += 1024) s += x[i] * x[i];
-  const double xn2 = block_sum<1024>(s, red);
+  for (int64_t i = 1 + threadIdx.x; i < m; i += 256) s += x[i] * x[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  const double xn2 = red[0] + red[1] + red[2] + red[3];
   const double alpha = x[0];
-  double beta, t, scale;
   if (xn2 == 0.0) {
-    t = 0.0;
+    tau_k = 0.0;
     beta = alpha;
     scale = 0.0;
   } else {
     beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-    t = (beta - alpha) / beta;
+    tau_k = (beta - alpha) / beta;
     scale = 1.0 / (alpha - beta);
-  }
-  __syncthreads();
-  for (int64_t i = 1 + threadIdx.x; i < m; i += 1024) x[i] *= scale;
-  if (threadIdx.x == 0) {
-    if (!isfinite(beta) || !isfinite(t)) atomicExch(nonfinite, 1);
-    x[0] = 1.0;
-    tau[k] = t;
-    d[k] = A[k * n + k];
-    e[k] = beta;
   }
 }
 
-// p_i = tau * sum_j A[i][j] v_j over the trailing block (one wave per row);
-// pv_i = p_i * v_i for the correction scalar.
-__global__ __launch_bounds__(256) void symv_kernel(const double *A, int64_t n, int64_t k,
-                                                   const double *tau, double *p, double *pv) {
+// p = tau * A22 v (one wave per row of the trailing block), pv = p .* v
+__global__ __launch_bounds__(256) void house_symv_kernel(const double *A, int64_t n, int64_t k,
+                                                         double *V, double *tau, double *d,
+                                                         double *e, double *p, double *pv,
+                                                         int *nonfinite) {
+  __shared__ double red[4];
   const int64_t m = n - k - 1;
+  const double *x = A + k * n + k + 1;
+  double t, scale, beta;
+  reflector(x, m, red, t, scale, beta);
+  if (blockIdx.x == 0) {
+    double *v = V + k * n + k + 1;
+    for (int64_t i = threadIdx.x; i < m; i += 256) v[i] = i == 0 ? 1.0 : x[i] * scale;
+    if (threadIdx.x == 0) {
+      if (!isfinite(beta) || !isfinite(t)) atomicExch(nonfinite, 1);
+      tau[k] = t;
+      d[k] = A[k * n + k];
+      e[k] = beta;
+    }
+  }
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= m) return;
-  const double *v = A + k * n + k + 1;
   const double *row = A + (k + 1 + r) * n + k + 1;
   double s = 0.0;
-  for (int64_t j = lane; j < m; j += 64) s += row[j] * v[j];
+  for (int64_t j = lane; j < m; j += 64) s += row[j] * (j == 0 ? 1.0 : x[j] * scale);
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   if (lane == 0) {
-    const double pi = tau[k] * s;
+    const double pi = t * s;
     p[r] = pi;
-    pv[r] = pi * v[r];
+    pv[r] = pi * (r == 0 ? 1.0 : x[r] * scale);
   }
 }
 
-// w = p - (tau/2)(p.v) v
-__global__ __launch_bounds__(1024) void wvec_kernel(const double *A, int64_t n, int64_t k,
-                                                    const double *tau, const double *p,
-                                                    const double *pv, double *w) {
-  __shared__ double red[1024 / 64 + 1];
+// A22 -= v w^T + w v^T with w = p - (tau/2)(p.v) v; each work-group reduces p.v
+// itself (fixed order) and updates a band of 16 rows
+__global__ __launch_bounds__(256) void rank2_fused_kernel(double *A, int64_t n, int64_t k,
+                                                          const double *V, const double *tau,
+                                                          const double *p, const double *pv) {
+  __shared__ double red[4];
   const int64_t m = n - k - 1;
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += 1024) s += pv[i];
-  const double K = 0.5 * tau[k] * block_sum<1024>(s, red);
-  const double *v = A + k * n + k + 1;
-  for (int64_t i = threadIdx.x; i < m; i += 1024) w[i] = p[i] - K * v[i];
-}
-
-// A22 -= v w^T + w v^T
-__global__ __launch_bounds__(256) void rank2_kernel(double *A, int64_t n, int64_t k, const double *w) {
-  const int64_t m = n - k - 1;
-  const double *v = A + k * n + k + 1;
-  const int64_t total = m * m;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-    const int64_t i = e / m, j = e % m;
-    double *a = A + (k + 1 + i) * n + k + 1 + j;
-    *a = *a - (v[i] * w[j] + w[i] * v[j]);
+  for (int64_t i = threadIdx.x; i < m; i += 256) s += pv[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  const double K = 0.5 * tau[k] * (red[0] + red[1] + red[2] + red[3]);
+  const double *v = V + k * n + k + 1;
+  const int64_t r0 = (int64_t)blockIdx.x * 16, r1 = min(m, r0 + 16);
+  for (int64_t i = r0; i < r1; ++i) {
+    const double vi = v[i], wi = p[i] - K * vi;
+    double *row = A + (k + 1 + i) * n + k + 1;
+    for (int64_t j = threadIdx.x; j < m; j += 256) {
+      const double wj = p[j] - K * v[j];
+      row[j] = row[j] - (vi * wj + wi * v[j]);
+    }
   }
 }
 
@@ -145,30 +151,49 @@ __device__ inline int sturm_count(const double *d, const double *e, int64_t n, d
   return cnt;
 }
 
-// lambda[j] = j-th smallest eigenvalue of T, one thread per j
+// lambda[j] = j-th smallest eigenvalue of T, one wave per j: each step the 64
+// lanes evaluate Sturm counts at 64 interior points of the bracket, which then
+// shrinks by a factor 65 (multisection).
 __global__ __launch_bounds__(256) void bisect_kernel(const double *d, const double *e, int64_t n,
                                                      double *lambda, double *tnorm_out) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= n) return;
-  double lo = d[0], hi = d[0], emax2 = 0.0;
-  for (int64_t i = 0; i < n; ++i) {
+  double lo = INFINITY, hi = -INFINITY, emax2 = 0.0;
+  for (int64_t i = lane; i < n; i += 64) {
     const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
     lo = fmin(lo, d[i] - r);
     hi = fmax(hi, d[i] + r);
     if (i + 1 < n) emax2 = fmax(emax2, e[i] * e[i]);
   }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+    emax2 = fmax(emax2, __shfl_xor(emax2, o, 64));
+  }
   const double tnorm = fmax(fabs(lo), fabs(hi));
   const double pivmin = SAFMIN * fmax(1.0, emax2);
   lo -= 2.0 * EPS * tnorm * n + pivmin;
   hi += 2.0 * EPS * tnorm * n + pivmin;
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (hi - lo <= 2.0 * EPS * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin || mid == lo || mid == hi) break;
-    if (sturm_count(d, e, n, mid, pivmin) > j) hi = mid;
-    else lo = mid;
+  for (int it = 0; it < 40; ++it) {
+    if (hi - lo <= 2.0 * EPS * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin) break;
+    const double h = (hi - lo) / 65.0;
+    const double x = lo + h * (lane + 1);
+    const bool above = sturm_count(d, e, n, x, pivmin) > j;     // lambda_j < x
+    const unsigned long long mask = __ballot(above);
+    if (mask == 0ull) {
+      lo = lo + h * 64;                                        // lambda_j in [x_63, hi]
+    } else {
+      const int t = __ffsll((long long)mask) - 1;               // first point above lambda_j
+      const double new_hi = lo + h * (t + 1);
+      lo = t > 0 ? lo + h * t : lo;
+      hi = new_hi;
+    }
   }
-  lambda[j] = 0.5 * (lo + hi);
-  if (j == 0) *tnorm_out = tnorm;
+  if (lane == 0) {
+    lambda[j] = 0.5 * (lo + hi);
+    if (j == 0) *tnorm_out = tnorm;
+  }
 }
 
 __device__ inline double start_value(int64_t i, int64_t j) {
@@ -182,44 +207,42 @@ __device__ inline double start_value(int64_t i, int64_t j) {
 // Eigenvector of T for lambda[j] by three steps of inverse iteration; thread j
 // owns column j of Zt (row-major n x n) and columns j of the factor arrays
 // (element i of thread j at [i*n + j], so a wave's accesses are contiguous).
-__global__ __launch_bounds__(256) void inverse_iteration_kernel(
+// The LU factorisation of T - lambda I with partial pivoting and both triangular
+// solves carry their running values in registers; memory is only written
+// (factorisation) or read (solves) once per element.
+// The shift is lambda_j - delta, delta = 1e-10 |T|: eigenvalues that are equal to
+// working precision (computed values differing by ~1e-14 |T|) are then amplified
+// alike, so their vectors stay independent combinations of the common eigenspace
+// instead of collapsing onto one eigenvector; an isolated eigenvalue at gap g
+// still converges by (delta/g)^3 in three steps.
+__global__ __launch_bounds__(64) void inverse_iteration_kernel(
     const double *d, const double *e, int64_t n, const double *lambda, const double *tnorm,
     double *Zt, double *dg, double *du, double *du2, double *dl, double *swp) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (j >= n) return;
-  const double lam = lambda[j];
   const double tiny = EPS * fmax(*tnorm, SAFMIN * 1e16);
+  const double lam = lambda[j] - 1e-10 * fmax(*tnorm, SAFMIN * 1e16);
 #define AT(arr, i) arr[(int64_t)(i) * n + j]
-  // LU with partial pivoting of T - lam I
-  for (int64_t i = 0; i < n; ++i) {
-    AT(dg, i) = d[i] - lam;
-    if (i + 1 < n) { AT(du, i) = e[i]; AT(dl, i) = e[i]; }
-    if (i + 2 < n) AT(du2, i) = 0.0;
-  }
+  // factorisation: g = current pivot candidate of row i, u = its superdiagonal
+  double g = d[0] - lam, u = n > 1 ? e[0] : 0.0;
   for (int64_t i = 0; i + 1 < n; ++i) {
-    const double gi = AT(dg, i), li = AT(dl, i);
-    if (fabs(gi) >= fabs(li)) {
-      const double g = gi != 0.0 ? gi : tiny;
-      AT(dg, i) = g;
-      const double f = li / g;
-      AT(dl, i) = f;
-      AT(dg, i + 1) = AT(dg, i + 1) - f * AT(du, i);
-      AT(swp, i) = 0.0;
+    const double l = e[i], dn = d[i + 1] - lam, en = i + 2 < n ? e[i + 1] : 0.0;
+    if (fabs(g) >= fabs(l)) {
+      const double gp = g != 0.0 ? g : tiny;
+      const double f = l / gp;
+      AT(dg, i) = gp; AT(dl, i) = f; AT(du, i) = u; AT(swp, i) = 0.0;
+      if (i + 2 < n) AT(du2, i) = 0.0;
+      g = dn - f * u;
+      u = en;
     } else {
-      const double f = gi / li;
-      AT(dg, i) = li;
-      AT(dl, i) = f;
-      const double tmp = AT(du, i);
-      AT(du, i) = AT(dg, i + 1);
-      AT(dg, i + 1) = tmp - f * AT(dg, i + 1);
-      if (i + 2 < n) {
-        AT(du2, i) = AT(du, i + 1);
-        AT(du, i + 1) = -f * AT(du, i + 1);
-      }
-      AT(swp, i) = 1.0;
+      const double f = g / l;
+      AT(dg, i) = l; AT(dl, i) = f; AT(du, i) = dn; AT(swp, i) = 1.0;
+      if (i + 2 < n) AT(du2, i) = en;
+      g = u - f * dn;
+      u = -f * en;
     }
   }
-  if (AT(dg, n - 1) == 0.0) AT(dg, n - 1) = tiny;
+  AT(dg, n - 1) = g != 0.0 ? g : tiny;
   double nrm = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     const double s = start_value(i, j);
@@ -228,22 +251,28 @@ __global__ __launch_bounds__(256) void inverse_iteration_kernel(
   }
   for (int it = 0; it < 3; ++it) {
     const double inv = 1.0 / sqrt(nrm);
-    // forward: apply row swaps and multipliers (L y = P b)
-    for (int64_t i = 0; i < n; ++i) AT(Zt, i) *= inv;
+    // forward: row interchanges and multipliers (L y = P b)
+    double cur = AT(Zt, 0) * inv;
     for (int64_t i = 0; i + 1 < n; ++i) {
-      double bi = AT(Zt, i), bn = AT(Zt, i + 1);
-      if (AT(swp, i) != 0.0) { const double t = bi; bi = bn; bn = t; AT(Zt, i) = bi; }
-      AT(Zt, i + 1) = bn - AT(dl, i) * bi;
+      const double nxt = AT(Zt, i + 1) * inv;
+      double bi = cur, bn = nxt;
+      if (AT(swp, i) != 0.0) { bi = nxt; bn = cur; }
+      AT(Zt, i) = bi;
+      cur = bn - AT(dl, i) * bi;
     }
+    AT(Zt, n - 1) = cur;
     // backward: U x = y
     nrm = 0.0;
+    double x1 = 0.0, x2 = 0.0;
     for (int64_t i = n - 1; i >= 0; --i) {
       double s = AT(Zt, i);
-      if (i + 1 < n) s -= AT(du, i) * AT(Zt, i + 1);
-      if (i + 2 < n) s -= AT(du2, i) * AT(Zt, i + 2);
+      if (i + 1 < n) s -= AT(du, i) * x1;
+      if (i + 2 < n) s -= AT(du2, i) * x2;
       const double xi = s / AT(dg, i);
       AT(Zt, i) = xi;
       nrm += xi * xi;
+      x2 = x1;
+      x1 = xi;
     }
     if (!(nrm > 0.0) || !isfinite(nrm)) {  // fall back to a fresh start
       nrm = 0.0;
@@ -265,12 +294,12 @@ __global__ __launch_bounds__(256) void inverse_iteration_kernel(
 constexpr int WY_NB = 64;
 
 // Vt row j = v_{k0+j} (zero at and above position k0+j, 1 at k0+j+1)
-__global__ __launch_bounds__(256) void wy_vrows_kernel(const double *A, int64_t n, int64_t k0,
+__global__ __launch_bounds__(256) void wy_vrows_kernel(const double *V, int64_t n, int64_t k0,
                                                        int nb, double *Vt) {
   const int64_t total = (int64_t)nb * n;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
     const int64_t j = e / n, i = e % n, k = k0 + j;
-    Vt[e] = i > k ? A[k * n + i] : 0.0;
+    Vt[e] = i > k ? V[k * n + i] : 0.0;
   }
 }
 
@@ -364,26 +393,29 @@ hipError_t run_syev(int64_t n, const double *Ain, int64_t lda, double *lambda, d
   double *M = (double *)(w + L.m), *chol = (double *)(w + L.chol);
   double *partial = (double *)(w + L.partial), *vec = (double *)(w + L.vec);
   double *tau = vec, *d = vec + n, *e = vec + 2 * n, *p = vec + 3 * n, *pv = vec + 4 * n;
-  double *wv = vec + 5 * n, *tnorm = vec + 8 * n;
+  double *tnorm = vec + 8 * n;
   int *info = (int *)(w + L.info);
   hipError_t err;
   hipLaunchKernelGGL(clear_ints_kernel, dim3(1), dim3(64), 0, s, info, 4);
   hipLaunchKernelGGL(copy_matrix_kernel, dim3(grid_for(n * n)), dim3(256), 0, s, Ain, lda, A, n, n);
-  // 1. tridiagonalisation
+  // 1. tridiagonalisation; reflector vectors go to V (rows k, columns k+1..)
+  double *V = du2;
   for (int64_t k = 0; k + 2 < n; ++k) {
     const int64_t m = n - k - 1;
-    hipLaunchKernelGGL(house_kernel, dim3(1), dim3(1024), 0, s, A, n, k, tau, d, e, info + 1);
-    hipLaunchKernelGGL(symv_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, A, n, k, tau, p, pv);
-    hipLaunchKernelGGL(wvec_kernel, dim3(1), dim3(1024), 0, s, A, n, k, tau, p, pv, wv);
-    hipLaunchKernelGGL(rank2_kernel, dim3(grid_for(m * m)), dim3(256), 0, s, A, n, k, wv);
+    hipLaunchKernelGGL(house_symv_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, A, n, k,
+                       V, tau, d, e, p, pv, info + 1);
+    hipLaunchKernelGGL(rank2_fused_kernel, dim3((unsigned)((m + 15) / 16)), dim3(256), 0, s, A, n, k,
+                       V, tau, p, pv);
   }
   hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(64), 0, s, A, n, d, e);
   // 2. eigenvalues
-  hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, e, n,
+  hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d, e, n,
                      lambda, tnorm);
   // 3. eigenvectors of T
-  hipLaunchKernelGGL(inverse_iteration_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                     d, e, n, lambda, tnorm, Zt, dg, du, du2, dl, swp);
+  // V (held in du2) is still needed, so the second superdiagonal of the factors
+  // goes to Z2, which is free until the re-orthonormalisation below
+  hipLaunchKernelGGL(inverse_iteration_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s,
+                     d, e, n, lambda, tnorm, Zt, dg, du, Z2, dl, swp);
   // 4. Cholesky-QR twice: Zt <- Zt M
   for (int pass = 0; pass < 2; ++pass) {
     double *src = pass == 0 ? Zt : Z2, *dst = pass == 0 ? Z2 : Zt;
@@ -402,7 +434,7 @@ hipError_t run_syev(int64_t n, const double *Ain, int64_t lda, double *lambda, d
     for (int64_t k0 = (R > 0 ? (R - 1) / WY_NB * WY_NB : -1); k0 >= 0; k0 -= WY_NB) {
       const int nb = (int)std::min<int64_t>(WY_NB, R - k0);
       const int64_t m = n - k0 - 1;                 // rows touched
-      hipLaunchKernelGGL(wy_vrows_kernel, dim3(grid_for((int64_t)nb * n)), dim3(256), 0, s, A, n, k0, nb, Vt);
+      hipLaunchKernelGGL(wy_vrows_kernel, dim3(grid_for((int64_t)nb * n)), dim3(256), 0, s, V, n, k0, nb, Vt);
       hipLaunchKernelGGL(wy_gram_kernel, dim3((unsigned)((nb * nb + 3) / 4)), dim3(256), 0, s, Vt, n, k0, nb, Gw);
       hipLaunchKernelGGL(wy_t_kernel, dim3(1), dim3(64), 0, s, Gw, tau, k0, nb, Tw);
       // W = V^T Z[k0+1:, :]   (nb x n)

@@ -340,3 +340,28 @@ ttdft_status ttdft_rayleigh_ritz(const ttdft_bsr *H, const void *Y, int64_t ldy,
 }
 
 }  // extern "C"
+
+extern "C" {
+
+size_t ttdft_lanczos_workspace(const ttdft_bsr *H, int32_t k) {
+  if (!H || H->n_block_rows < 1 || k < 1) return 0;
+  return lanczos_work_bytes(H->n_block_rows * 64, k);
+}
+
+ttdft_status ttdft_lanczos_upper_bound(const ttdft_bsr *H, const int64_t *perm, int32_t k,
+                                       uint64_t seed, double *bound, void *work,
+                                       size_t work_bytes, void *stream) {
+  ttdft_status st = check_h64(H);
+  if (st != TTDFT_OK) return st;
+  if (!perm || !bound) return failf(TTDFT_ERR_NULL, "perm or bound is NULL");
+  if (k < 1 || k > 1000) return failf(TTDFT_ERR_SHAPE, "k = %d outside 1 .. 1000", k);
+  const size_t need = lanczos_work_bytes(H->n_block_rows * 64, k);
+  if (!work || work_bytes < need) return failf(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", need);
+  hipError_t e = run_lanczos_bound(*H, perm, k, seed, work, (hipStream_t)stream, bound);
+  if (e != hipSuccess) return hip_fail(e, "lanczos");
+  if (!std::isfinite(bound[0]) || !std::isfinite(bound[1]) || !std::isfinite(bound[2]))
+    return failf(TTDFT_ERR_NONFINITE, "non-finite Lanczos estimate");
+  return api_ok();
+}
+
+}  // extern "C"

@@ -4,7 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstddef>
-#include "../../include/ttdft.h"
+#include "ttdft.h"
 
 namespace ttdft {
 
@@ -79,5 +79,11 @@ hipError_t run_syev(int64_t n, const double *A, int64_t lda, double *lambda, dou
 hipError_t launch_sddmm(const ttdft_bsr &H, const void *Abar, int64_t lda, const void *Bk,
                         int64_t ldb, int64_t n_vec, double coef, void *dH, const uint64_t *mask,
                         bool accumulate, ttdft_dtype xt, hipStream_t s);
+
+// ---- Lanczos estimate of the top of the spectrum
+// host_out: theta_max, theta_max + |beta_{k+1} s_k|, theta_max + beta_{k+1}
+size_t lanczos_work_bytes(int64_t rows, int k);
+hipError_t run_lanczos_bound(const ttdft_bsr &H, const int64_t *perm, int k, uint64_t seed,
+                             void *work, hipStream_t s, double host_out[3]);
 
 }  // namespace ttdft

@@ -226,3 +226,14 @@ def test_backward_workspace_plan(lib_built):
     assert ws(16, 4) == blk * (1 + 7 + 2)            # pairs {1,4,5,8,9,12,13} + 2 segment slots
     assert ws(1, 4) == blk                           # nothing to store
     assert ws(16, 4) < ws(16, 0)
+
+
+def test_lanczos_validation(lib_built):
+    L = _lib()
+    lib = L.load()
+    H64, H32 = _fake_bsr(), _fake_bsr(dtype=1)
+    out = (C.c_double * 3)()
+    assert L.STATUS[lib.ttdft_lanczos_upper_bound(C.byref(H32), FAKE, 10, 0, out, FAKE, 1 << 30, None)] == "TTDFT_ERR_DTYPE"
+    assert L.STATUS[lib.ttdft_lanczos_upper_bound(C.byref(H64), FAKE, 0, 0, out, FAKE, 1 << 30, None)] == "TTDFT_ERR_SHAPE"
+    assert L.STATUS[lib.ttdft_lanczos_upper_bound(C.byref(H64), None, 10, 0, out, FAKE, 1 << 30, None)] == "TTDFT_ERR_NULL"
+    assert L.STATUS[lib.ttdft_lanczos_upper_bound(C.byref(H64), FAKE, 10, 0, out, FAKE, 8, None)] == "TTDFT_ERR_WORKSPACE"
