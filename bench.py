@@ -31,8 +31,8 @@ PEAK_HBM_GBS = 8000.0
 # see profiles/cheb_step_f64_lattice60_h4_n2048_m20_bytes.md.  Valid only while the
 # kernel source is the one that was profiled.
 COUNTED_TRAFFIC = {
-    ("f64", "lattice60_h4_n2048_m20"): {"read_bytes": 111.49e9, "write_bytes": 3.539e9,
-                                        "kernel_sha256_16": "f6c7b3d66daecc34"},
+    ("f64", "lattice60_h4_n2048_m20"): {"read_bytes": 96.719e9, "write_bytes": 3.539e9,
+                                        "kernel_sha256_16": "f583dac5d449c4df"},
 }
 
 
@@ -313,8 +313,9 @@ def main():
         "hbm_gbs_algorithmic": round(alg_bytes_launch / launch_s / 1e9, 1),
         "issued_tflops": round(issued_flops_launch / launch_s / 1e12, 2),
         "issued_frac": round(issued_flops_launch / launch_s / 1e12 / peak, 4),
-        "roofline": {"bound": "mfma", "kernel": "cheb_step_f64_pipe" if args.precision == "f64"
-                     else ("cheb_step_mfma4<float>" if args.precision == "f32" else "cheb_step_bf16<float>"),
+        "roofline": {"bound": "mfma", "kernel": "cheb_step_pipe<double, 1>" if args.precision == "f64"
+                     else ("cheb_step_pipe<float, 1>" if args.precision == "f32"
+                           else "cheb_step_bf16_pipe<float>"),
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic,
                      "per_launch": {"alg_flops": alg_flops_launch, "alg_bytes": alg_bytes_launch,

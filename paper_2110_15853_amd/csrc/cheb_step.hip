@@ -50,7 +50,7 @@ template <> struct Mfma4<float> {
 //    tile is fetched into registers while the current one is contracted (one
 //    barrier per tile).
 //  - B operand (Y_k panel): each wave reads its own 16 vectors straight from
-//    global memory into registers, half a tile (8 k-steps) ahead of use.
+//    global memory into registers, a whole tile (16 k-steps) ahead of use.
 constexpr int F64_NV = 128, F64_THREADS = 512, F64_S = 65;   // fragment row stride (+1 pad)
 // launch order: column groups of ORDER_CGROUP tiles outermost; each XCD takes runs
 // of ORDER_CHUNK consecutive block rows (all column tiles of the group), the 8
@@ -58,8 +58,6 @@ constexpr int F64_NV = 128, F64_THREADS = 512, F64_S = 65;   // fragment row str
 constexpr int ORDER_CGROUP = 16, ORDER_CHUNK = 1;
 // column blocks of 16 vectors per wave in the FP64 / FP32 kernel
 constexpr int PIPE_CB_F64 = 1, PIPE_CB_F32 = 1;
-// prefetch the next tile's Y_k fragments a whole tile ahead (else one quarter)
-constexpr bool PIPE_DEEP = true;
 // waves per SIMD the kernel is compiled for (register budget 512 / waves)
 template <typename T, int CB> constexpr int pipe_waves() { return (sizeof(T) == 8 && CB > 1) ? 2 : 4; }
 
@@ -125,112 +123,112 @@ __global__ __launch_bounds__(F64_THREADS, (pipe_waves<T, CB>())) void cheb_step_
   };
   const int rd_slot = (lane & 48) + (((lane & 15) + (lane >> 4)) & 15);
   // quarter qq (k-steps 4qq .. 4qq+3, panel rows 16qq .. 16qq+15) of the Y_k panel of tile t
+  // Columns past n_vec (last column tile) read a clamped, in-range column: an
+  // output column of the matrix-core product depends only on its own B column,
+  // and those columns are never stored.  Unconditional loads keep the prefetch
+  // asynchronous (a per-lane guard makes the compiler wait for each load).
+  int64_t colc[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) colc[cb] = min(col0 + 16 * cb, n_vec - 1);
   auto load_b = [&](int t, int qq, T (&dst)[CB][4]) {
-    const T *Xp = Yk + ((int64_t)tcol[t] * 64 + 16 * qq + krow) * ldk + col0;
+    const T *Xp = Yk + ((int64_t)tcol[t] * 64 + 16 * qq + krow) * ldk;
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      const bool ok = col0 + 16 * cb < n_vec;
+    for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) dst[cb][q] = ok ? Xp[(int64_t)(4 * q) * ldk + 16 * cb] : T(0);
-    }
+      for (int q = 0; q < 4; ++q) dst[cb][q] = Xp[(int64_t)(4 * q) * ldk + colc[cb]];
   };
   // all-zero 16x4 sub-blocks of the tile (bit clear in fm) are skipped; fm is
-  // uniform over the work-group, so the branch costs no divergence
+  // uniform over the work-group, so the branch costs no divergence.  The four A
+  // fragments of a k-step are read from LDS before the branches so the reads are
+  // not serialised behind them.
   auto mma_quarter = [&](const T *sA, int qq, const T (&bq)[CB][4], uint64_t fm) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int kk = 4 * qq + q;
+      T a[4];
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) a[mb] = sA[(kk * 4 + mb) * F64_S + rd_slot];
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb)
         if ((fm >> (kk * 4 + mb)) & 1ull) {
-          const T a = sA[(kk * 4 + mb) * F64_S + rd_slot];
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) acc[cb][mb] = M::op(a, bq[cb][q], acc[cb][mb]);
+          for (int cb = 0; cb < CB; ++cb) acc[cb][mb] = M::op(a[mb], bq[cb][q], acc[cb][mb]);
         }
     }
   };
+  auto tile_mask = [&](int t) -> uint64_t { return frag_mask ? frag_mask[t] : ~0ull; };
 
-  if constexpr (PIPE_DEEP) {
-    // whole-tile prefetch: quarters 0..3 of tile t+1 are fetched while tile t is contracted
-    T b2[CB][4], b3[CB][4];
-    if (t_begin < t_end) {
-      load_b(t_begin, 0, b0);
-      load_b(t_begin, 1, b1);
-      load_b(t_begin, 2, b2);
-      load_b(t_begin, 3, b3);
-      load_h(t_begin, 0);
-      store_h(0, 0);
-      load_h(t_begin, 1);
-      store_h(0, 1);
-      __syncthreads();
-    }
-    int buf = 0;
-    for (int t = t_begin; t < t_end; ++t) {
-      const bool more = t + 1 < t_end;
-      const T *sA = sH[buf];
-      const uint64_t fm = frag_mask ? frag_mask[t] : ~0ull;
-      if (more) load_h(t + 1, 0);
-      mma_quarter(sA, 0, b0, fm);
-      if (more) load_b(t + 1, 0, b0);
-      if (more) store_h(buf ^ 1, 0);
-      mma_quarter(sA, 1, b1, fm);
-      if (more) load_b(t + 1, 1, b1);
-      if (more) load_h(t + 1, 1);
-      mma_quarter(sA, 2, b2, fm);
-      if (more) load_b(t + 1, 2, b2);
-      if (more) store_h(buf ^ 1, 1);
-      mma_quarter(sA, 3, b3, fm);
-      if (more) load_b(t + 1, 3, b3);
-      __syncthreads();
-      buf ^= 1;
-    }
-  } else {
+  // Software pipeline over the block row's tiles: while tile t is contracted from
+  // LDS buffer buf, tile t+1 is fetched into registers (H in two halves, stored to
+  // the other buffer; the Y_k panel in quarters, each refilled as soon as its
+  // quarter of tile t is done).  All loads are unconditional: on the last tile
+  // the "next" tile is the last tile again, so no value is undefined on any path
+  // and the compiler keeps the loads in flight instead of waiting on them.
   if (t_begin < t_end) {
-      load_b(t_begin, 0, b0);
-      load_b(t_begin, 1, b1);
-      load_h(t_begin, 0);
-      store_h(0, 0);
-      load_h(t_begin, 1);
-      store_h(0, 1);
-      __syncthreads();
-    }
+    T b2[CB][4], b3[CB][4];
+    load_b(t_begin, 0, b0);
+    load_b(t_begin, 1, b1);
+    load_b(t_begin, 2, b2);
+    load_b(t_begin, 3, b3);
+    load_h(t_begin, 0);
+    store_h(0, 0);
+    load_h(t_begin, 1);
+    store_h(0, 1);
+    uint64_t fm = tile_mask(t_begin);
+    __syncthreads();
     int buf = 0;
     for (int t = t_begin; t < t_end; ++t) {
-      const bool more = t + 1 < t_end;
+      const int tn = min(t + 1, t_end - 1);
+      const uint64_t fm_next = tile_mask(tn);
       const T *sA = sH[buf];
-      const uint64_t fm = frag_mask ? frag_mask[t] : ~0ull;
-      if (more) load_h(t + 1, 0);
+      load_h(tn, 0);
       mma_quarter(sA, 0, b0, fm);
-      load_b(t, 2, b0);
-      if (more) store_h(buf ^ 1, 0);
+      load_b(tn, 0, b0);
+      store_h(buf ^ 1, 0);
       mma_quarter(sA, 1, b1, fm);
-      load_b(t, 3, b1);
-      if (more) load_h(t + 1, 1);
-      mma_quarter(sA, 2, b0, fm);
-      if (more) load_b(t + 1, 0, b0);
-      if (more) store_h(buf ^ 1, 1);
-      mma_quarter(sA, 3, b1, fm);
-      if (more) load_b(t + 1, 1, b1);
+      load_b(tn, 1, b1);
+      load_h(tn, 1);
+      mma_quarter(sA, 2, b2, fm);
+      load_b(tn, 2, b2);
+      store_h(buf ^ 1, 1);
+      mma_quarter(sA, 3, b3, fm);
+      load_b(tn, 3, b3);
       __syncthreads();
       buf ^= 1;
+      fm = fm_next;
     }
-  
   }
 
+  // epilogue: all loads of the 64 x 16 slab first, then the stores
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb) {
     const int64_t col = col0 + 16 * cb;
-    if (col >= n_vec) continue;
+    T yk[4][4], yp[4][4];
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
+    for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t grow = B * 64 + 16 * mb + M::row(lane, q);
-        const T y = Yk[grow * ldk + col];
-        T out = alpha * (acc[cb][mb][q] - c * y);
-        if (beta != T(0)) out -= beta * Yp[grow * ldp + col];
-        Yo[grow * ldo + col] = out;
-      }
+      for (int q = 0; q < 4; ++q)
+        yk[mb][q] = Yk[(B * 64 + 16 * mb + M::row(lane, q)) * ldk + colc[cb]];
+    if (beta != T(0)) {
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          yp[mb][q] = Yp[(B * 64 + 16 * mb + M::row(lane, q)) * ldp + colc[cb]];
+    } else {
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) yp[mb][q] = T(0);
+    }
+    if (col < n_vec) {
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t grow = B * 64 + 16 * mb + M::row(lane, q);
+          Yo[grow * ldo + col] = alpha * (acc[cb][mb][q] - c * yk[mb][q]) - beta * yp[mb][q];
+        }
     }
   }
 }

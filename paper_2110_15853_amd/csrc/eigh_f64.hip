@@ -69,7 +69,8 @@ __device__ inline void reflector(const double *x, int64_t m, double *red, double
   }
 }
 
-// p = tau * A22 v (one wave per row of the trailing block), pv = p .* v
+// p = tau * A22 v (one wave per row of the trailing block); pv[b] = the sum of
+// p_r v_r over the rows of work-group b
 __global__ __launch_bounds__(256) void house_symv_kernel(const double *A, int64_t n, int64_t k,
                                                          double *V, double *tau, double *d,
                                                          double *e, double *p, double *pv,
@@ -89,35 +90,40 @@ __global__ __launch_bounds__(256) void house_symv_kernel(const double *A, int64_
       e[k] = beta;
     }
   }
-  const int lane = threadIdx.x & 63;
-  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= m) return;
-  const double *row = A + (k + 1 + r) * n + k + 1;
-  double s = 0.0;
-  for (int64_t j = lane; j < m; j += 64) s += row[j] * (j == 0 ? 1.0 : x[j] * scale);
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-  if (lane == 0) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t r = (int64_t)blockIdx.x * 4 + wv;
+  __shared__ double part[4];
+  double pvr = 0.0;
+  if (r < m) {
+    const double *row = A + (k + 1 + r) * n + k + 1;
+    double s = 0.0;
+    for (int64_t j = lane; j < m; j += 64) s += row[j] * (j == 0 ? 1.0 : x[j] * scale);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
     const double pi = t * s;
-    p[r] = pi;
-    pv[r] = pi * (r == 0 ? 1.0 : x[r] * scale);
+    pvr = pi * (r == 0 ? 1.0 : x[r] * scale);
+    if (lane == 0) p[r] = pi;
   }
+  if (lane == 0) part[wv] = pvr;
+  __syncthreads();
+  // pv holds one partial sum of p.v per work-group, summed in a fixed order later
+  if (threadIdx.x == 0) pv[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
 }
 
-// A22 -= v w^T + w v^T with w = p - (tau/2)(p.v) v; each work-group reduces p.v
-// itself (fixed order) and updates a band of 16 rows
+// A22 -= v w^T + w v^T with w = p - (tau/2)(p.v) v; each work-group sums the
+// per-work-group partials of p.v (fixed order) and updates a band of 4 rows
 __global__ __launch_bounds__(256) void rank2_fused_kernel(double *A, int64_t n, int64_t k,
                                                           const double *V, const double *tau,
                                                           const double *p, const double *pv) {
   __shared__ double red[4];
-  const int64_t m = n - k - 1;
+  const int64_t m = n - k - 1, nparts = (m + 3) / 4;
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += 256) s += pv[i];
+  for (int64_t i = threadIdx.x; i < nparts; i += 256) s += pv[i];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   const double K = 0.5 * tau[k] * (red[0] + red[1] + red[2] + red[3]);
   const double *v = V + k * n + k + 1;
-  const int64_t r0 = (int64_t)blockIdx.x * 16, r1 = min(m, r0 + 16);
+  const int64_t r0 = (int64_t)blockIdx.x * 4, r1 = min(m, r0 + 4);
   for (int64_t i = r0; i < r1; ++i) {
     const double vi = v[i], wi = p[i] - K * vi;
     double *row = A + (k + 1 + i) * n + k + 1;
@@ -293,48 +299,54 @@ __global__ __launch_bounds__(64) void inverse_iteration_kernel(
 // with T_jj = tau_j and T[0:j, j] = -tau_j T[0:j, 0:j] (V[:, 0:j]^T v_j).
 constexpr int WY_NB = 64;
 
-// Vt row j = v_{k0+j} (zero at and above position k0+j, 1 at k0+j+1)
-__global__ __launch_bounds__(256) void wy_vrows_kernel(const double *V, int64_t n, int64_t k0,
-                                                       int nb, double *Vt) {
+// Vb[i][j] = (v_{k0+j})_i, an n x nb row-major block: zero at and above row
+// k0+j, 1 at row k0+j+1
+__global__ __launch_bounds__(256) void wy_vblock_kernel(const double *V, int64_t n, int64_t k0,
+                                                        int nb, double *Vb) {
   const int64_t total = (int64_t)nb * n;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-    const int64_t j = e / n, i = e % n, k = k0 + j;
-    Vt[e] = i > k ? V[k * n + i] : 0.0;
+    const int64_t i = e / nb, j = e % nb, k = k0 + j;
+    Vb[e] = i > k ? V[k * n + i] : 0.0;
   }
 }
 
 // G[i][j] = v_i . v_j for i < j (one wave per pair)
-__global__ __launch_bounds__(256) void wy_gram_kernel(const double *Vt, int64_t n, int64_t k0,
+__global__ __launch_bounds__(256) void wy_gram_kernel(const double *Vb, int64_t n, int64_t k0,
                                                       int nb, double *G) {
   const int pair = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (pair >= nb * nb) return;
   const int i = pair / nb, j = pair % nb;
   if (i >= j) return;
   double s = 0.0;
-  for (int64_t x = k0 + 1 + j + lane; x < n; x += 64) s += Vt[(int64_t)i * n + x] * Vt[(int64_t)j * n + x];
+  for (int64_t x = k0 + 1 + j + lane; x < n; x += 64) s += Vb[x * nb + i] * Vb[x * nb + j];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   if (lane == 0) G[i * nb + j] = s;
 }
 
-// T from G and tau (one work-group, nb <= 64)
+// T from G and tau (one work-group, nb <= 64), in LDS
 __global__ __launch_bounds__(64) void wy_t_kernel(const double *G, const double *tau, int64_t k0,
                                                   int nb, double *T) {
+  __shared__ double sT[64][65], sG[64][65];
   const int i = threadIdx.x;
   for (int j = 0; j < nb; ++j) {
-    if (i < nb) T[i * nb + j] = 0.0;
+    if (i < nb) {
+      sT[i][j] = 0.0;
+      sG[i][j] = i < j ? G[i * nb + j] : 0.0;
+    }
   }
   __syncthreads();
   for (int j = 0; j < nb; ++j) {
     const double tj = tau[k0 + j];
     double s = 0.0;
-    if (i < j) {
-      for (int l = i; l < j; ++l) s += T[i * nb + l] * G[l * nb + j];
-    }
+    if (i < j)
+      for (int l = i; l < j; ++l) s += sT[i][l] * sG[l][j];
     __syncthreads();
-    if (i < j) T[i * nb + j] = -tj * s;
-    if (i == j) T[j * nb + j] = tj;
+    if (i < j) sT[i][j] = -tj * s;
+    if (i == j) sT[j][j] = tj;
     __syncthreads();
   }
+  for (int j = 0; j < nb; ++j)
+    if (i < nb) T[i * nb + j] = sT[i][j];
 }
 
 __global__ void clear_ints_kernel(int *p, int count) {
@@ -366,7 +378,7 @@ SyevLayout syev_layout(int64_t n) {
   L.g = take(npnp);
   L.m = take(npnp);
   L.chol = take(chol_rinv_scratch_doubles(n));
-  L.partial = take((size_t)L.splits * nn);
+  L.partial = take(std::max((size_t)L.splits * nn, (size_t)16 * WY_NB * n));
   L.vec = take(8 * (size_t)n + 8);
   L.info = take(4);
   L.wy = take(3 * (size_t)WY_NB * n + 2 * (size_t)WY_NB * WY_NB);
@@ -404,7 +416,7 @@ hipError_t run_syev(int64_t n, const double *Ain, int64_t lda, double *lambda, d
     const int64_t m = n - k - 1;
     hipLaunchKernelGGL(house_symv_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, A, n, k,
                        V, tau, d, e, p, pv, info + 1);
-    hipLaunchKernelGGL(rank2_fused_kernel, dim3((unsigned)((m + 15) / 16)), dim3(256), 0, s, A, n, k,
+    hipLaunchKernelGGL(rank2_fused_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, A, n, k,
                        V, tau, p, pv);
   }
   hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(64), 0, s, A, n, d, e);
@@ -429,21 +441,23 @@ hipError_t run_syev(int64_t n, const double *Ain, int64_t lda, double *lambda, d
   hipLaunchKernelGGL(copy_matrix_kernel, dim3(grid_for(n * n)), dim3(256), 0, s, Zt, n, Z, ldz, n);
   {
     const int64_t R = n - 2;                        // reflectors k = 0 .. n-3
-    double *Vt = (double *)(w + L.wy), *W = Vt + (int64_t)WY_NB * n, *W2 = Vt + 2 * (int64_t)WY_NB * n;
-    double *Gw = Vt + 3 * (int64_t)WY_NB * n, *Tw = Gw + WY_NB * WY_NB;
+    double *Vb = (double *)(w + L.wy), *W = Vb + (int64_t)WY_NB * n, *W2 = Vb + 2 * (int64_t)WY_NB * n;
+    double *Gw = Vb + 3 * (int64_t)WY_NB * n, *Tw = Gw + WY_NB * WY_NB;
+    double *wpart = partial;                        // split-K partials of W (free here)
     for (int64_t k0 = (R > 0 ? (R - 1) / WY_NB * WY_NB : -1); k0 >= 0; k0 -= WY_NB) {
       const int nb = (int)std::min<int64_t>(WY_NB, R - k0);
       const int64_t m = n - k0 - 1;                 // rows touched
-      hipLaunchKernelGGL(wy_vrows_kernel, dim3(grid_for((int64_t)nb * n)), dim3(256), 0, s, V, n, k0, nb, Vt);
-      hipLaunchKernelGGL(wy_gram_kernel, dim3((unsigned)((nb * nb + 3) / 4)), dim3(256), 0, s, Vt, n, k0, nb, Gw);
+      hipLaunchKernelGGL(wy_vblock_kernel, dim3(grid_for((int64_t)nb * n)), dim3(256), 0, s, V, n, k0, nb, Vb);
+      hipLaunchKernelGGL(wy_gram_kernel, dim3((unsigned)((nb * nb + 3) / 4)), dim3(256), 0, s, Vb, n, k0, nb, Gw);
       hipLaunchKernelGGL(wy_t_kernel, dim3(1), dim3(64), 0, s, Gw, tau, k0, nb, Tw);
-      // W = V^T Z[k0+1:, :]   (nb x n)
-      if ((err = launch_gemm_nn_ex(Vt + k0 + 1, n, Z + (k0 + 1) * ldz, ldz, nb, m, n, 1.0, W, n,
-                                   false, s)) != hipSuccess) return err;
+      // W = V^T Z[k0+1:, :]   (nb x n), split over the m rows
+      const int ws = (int)std::max<int64_t>(1, std::min<int64_t>(16, m / 128));
+      if ((err = launch_gemm_tn_general(Vb + (k0 + 1) * nb, nb, Z + (k0 + 1) * ldz, ldz, m, nb, n, W,
+                                        n, wpart, ws, s)) != hipSuccess) return err;
       // W2 = T W
       if ((err = launch_gemm_nn_ex(Tw, nb, W, n, nb, nb, n, 1.0, W2, n, false, s)) != hipSuccess) return err;
       // Z[k0+1:, :] -= V W2
-      if ((err = launch_gemm_tn_acc(Vt + k0 + 1, n, W2, n, nb, m, n, -1.0, Z + (k0 + 1) * ldz, ldz, s)) != hipSuccess)
+      if ((err = launch_gemm_nn_acc(Vb + (k0 + 1) * nb, nb, W2, n, m, nb, n, -1.0, Z + (k0 + 1) * ldz, ldz, s)) != hipSuccess)
         return err;
     }
   }

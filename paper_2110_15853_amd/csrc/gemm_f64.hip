@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(const double *__rest
 __global__ __launch_bounds__(THREADS, 2) void gemm_nn_kernel(
     const double *__restrict__ A, int64_t lda, const double *__restrict__ B, int64_t ldb,
     int64_t rows, int64_t K, int64_t N, double alpha, double *__restrict__ C, int64_t ldc,
-    int upper, int tiles_n, int64_t n_wg) {
+    int upper, int tiles_n, int64_t n_wg, int accumulate) {
   __shared__ double sA[2][BK][LDS_LD];
   __shared__ double sB[2][BK][LDS_LD];
   const int64_t L = xcd_group(blockIdx.x, n_wg, tiles_n);
@@ -204,9 +204,52 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_nn_kernel(
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int64_t row = i0 + 64 * wm + 16 * i + out_row(lane, t);
-        if (row < rows && col < N) C[row * ldc + col] = alpha * T.acc[i][j][t];
+        if (row < rows && col < N) {
+          const double v = alpha * T.acc[i][j][t];
+          C[row * ldc + col] = accumulate ? C[row * ldc + col] + v : v;
+        }
       }
     }
+}
+
+// general C[M x N] = A^T B, A: K x M, B: K x N, K split over grid.y (partials)
+__global__ __launch_bounds__(THREADS, 2) void gemm_tn_general_kernel(
+    const double *__restrict__ A, int64_t lda, const double *__restrict__ B, int64_t ldb,
+    int64_t K, int64_t M, int64_t N, double *__restrict__ partial, int64_t k_per_split,
+    int tiles_n) {
+  __shared__ double sA[2][BK][LDS_LD];
+  __shared__ double sB[2][BK][LDS_LD];
+  const int64_t tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  const int64_t i0 = tm * BM, j0 = tn * BN;
+  const int64_t kb = (int64_t)blockIdx.y * k_per_split, ke = min(K, kb + k_per_split);
+  Tile<true> T;
+  T.sA = sA;
+  T.sB = sB;
+  T.run(A, lda, B, ldb, i0, j0, kb, ke, M, N);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+  double *P = partial + (int64_t)blockIdx.y * M * N;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t col = j0 + 64 * wn + 16 * j + (lane & 15);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t row = i0 + 64 * wm + 16 * i + out_row(lane, t);
+        if (row < M && col < N) P[row * N + col] = T.acc[i][j][t];
+      }
+    }
+}
+
+__global__ __launch_bounds__(256) void reduce_general_kernel(const double *__restrict__ partial,
+                                                             int splits, int64_t M, int64_t N,
+                                                             double *C, int64_t ldc) {
+  const int64_t total = M * N;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    double v = 0.0;
+    for (int s = 0; s < splits; ++s) v += partial[(int64_t)s * total + e];
+    C[(e / N) * ldc + e % N] = v;
+  }
 }
 
 // C[M x N] += alpha * A^T B with A: K x M (lda), B: K x N (ldb), small K (no split)
@@ -297,7 +340,36 @@ hipError_t launch_gemm_nn_ex(const double *A, int64_t lda, const double *B, int6
   const int64_t g = tiles_m * tiles_n;
   if (g > 0x7fffffff) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(gemm_nn_kernel, dim3((unsigned)g), dim3(THREADS), 0, s, A, lda, B, ldb,
-                     rows, K, N, alpha, C, ldc, upper ? 1 : 0, tiles_n, g);
+                     rows, K, N, alpha, C, ldc, upper ? 1 : 0, tiles_n, g, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_nn_acc(const double *A, int64_t lda, const double *B, int64_t ldb,
+                              int64_t rows, int64_t K, int64_t N, double alpha, double *C,
+                              int64_t ldc, hipStream_t s) {
+  if (rows <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  const int tiles_n = (int)((N + BN - 1) / BN);
+  const int64_t g = ((rows + BM - 1) / BM) * tiles_n;
+  if (g > 0x7fffffff) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(gemm_nn_kernel, dim3((unsigned)g), dim3(THREADS), 0, s, A, lda, B, ldb,
+                     rows, K, N, alpha, C, ldc, 0, tiles_n, g, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_tn_general(const double *A, int64_t lda, const double *B, int64_t ldb,
+                                  int64_t K, int64_t M, int64_t N, double *C, int64_t ldc,
+                                  double *partial, int splits, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int tiles_n = (int)((N + BN - 1) / BN);
+  const int64_t tiles = ((M + BM - 1) / BM) * tiles_n;
+  int64_t kps = (K + splits - 1) / splits;
+  kps = (kps + BK - 1) / BK * BK;
+  hipLaunchKernelGGL(gemm_tn_general_kernel, dim3((unsigned)tiles, (unsigned)splits), dim3(THREADS),
+                     0, s, A, lda, B, ldb, K, M, N, partial, kps, tiles_n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned g = (unsigned)std::min<int64_t>((M * N + 255) / 256, 4096);
+  hipLaunchKernelGGL(reduce_general_kernel, dim3(g), dim3(256), 0, s, partial, splits, M, N, C, ldc);
   return hipGetLastError();
 }
 

@@ -55,6 +55,14 @@ hipError_t launch_gemm_nn_ex(const double *A, int64_t lda, const double *B, int6
                              int64_t rows, int64_t K, int64_t N, double alpha, double *C,
                              int64_t ldc, bool upper, hipStream_t s);
 hipError_t launch_clear_ints(int *p, int count, hipStream_t s);
+// C[rows x N] += alpha * A[rows x K] B[K x N]
+hipError_t launch_gemm_nn_acc(const double *A, int64_t lda, const double *B, int64_t ldb,
+                              int64_t rows, int64_t K, int64_t N, double alpha, double *C,
+                              int64_t ldc, hipStream_t s);
+// C[M x N] = A^T B, A: K x M, B: K x N, K split in `splits` (partial: splits*M*N doubles)
+hipError_t launch_gemm_tn_general(const double *A, int64_t lda, const double *B, int64_t ldb,
+                                  int64_t K, int64_t M, int64_t N, double *C, int64_t ldc,
+                                  double *partial, int splits, hipStream_t s);
 // C[M x N] += alpha * A^T B, A: K x M, B: K x N (small K, no split)
 hipError_t launch_gemm_tn_acc(const double *A, int64_t lda, const double *B, int64_t ldb,
                               int64_t K, int64_t M, int64_t N, double alpha, double *C,
