@@ -61,7 +61,10 @@ typedef enum { TTDFT_F64 = 0, TTDFT_F32 = 1, TTDFT_BF16 = 2 } ttdft_dtype;
  * The sparse symmetric Hamiltonian H^L of Sec. 3.3 has entries only between
  * nearby lattice sites (locality of the localized Tucker basis, Sec. 4.1).  Rows
  * are grouped by 4x4x4 lattice blocks into block rows of 64; each stored tile is
- * the dense 64x64 coupling between two blocks.
+ * the dense 64x64 coupling between two blocks.  Site (i, j, k) of the lattice
+ * lies in block ((i/4)*nb + j/4)*nb + k/4, nb = ceil(r/4), at local position
+ * 16*(2*((i%4)/2) + (j%4)/2) + 4*(2*(i%2) + j%2) + k%4: sixteen consecutive
+ * rows are a 2x2x4 box, four consecutive columns a line along k.
  */
 typedef struct {
   int64_t n_block_rows;        /* number of 64-row blocks; padded row count is 64*n_block_rows */

@@ -88,6 +88,13 @@ uint16_t f32_to_bf16_rne(float f) {
 }
 
 // ---- lattice blocking: natural index (i*r + j)*r + k -> (block, local)
+// Inside a 4x4x4 block the 64 sites are ordered so that every 16 consecutive
+// rows form a 2x2x4 box (i and j pairs, all four k) and every 4 consecutive
+// columns a line along k.  A matrix-core fragment (16 rows x 4 columns) then
+// couples a compact box to a line, and for a cube stencil more fragments of a
+// neighbouring block's tile are empty than with plain k-fastest order: 1200
+// instead of 1296 non-empty fragments per block row at h = 4, 768 instead of
+// 840 at h = 3.
 struct Lattice {
   int64_t r, nb;
   explicit Lattice(int64_t r_) : r(r_), nb((r_ + 3) / 4) {}
@@ -95,7 +102,9 @@ struct Lattice {
   void split(int64_t I, int64_t &blk, int64_t &loc) const {
     const int64_t i = I / (r * r), j = (I / r) % r, k = I % r;
     blk = ((i / 4) * nb + j / 4) * nb + k / 4;
-    loc = ((i % 4) * 4 + j % 4) * 4 + k % 4;
+    const int64_t box = ((i % 4) >> 1) * 2 + ((j % 4) >> 1);   // 2x2x4 box of the block
+    const int64_t line = (i & 1) * 2 + (j & 1);                 // k-line inside the box
+    loc = (box * 4 + line) * 4 + k % 4;
   }
 };
 
