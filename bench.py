@@ -171,7 +171,7 @@ def run_large(args, P, torch, workload):
                    "m": cfg.m, "h": cfg.h, "nnz": len(d), "tiles": H64.n_tiles,
                    "step": "one ChFSI pass: filter + FP64 Rayleigh-Ritz, bounds from the previous pass"},
         "passes": recs,
-        "roofline": {"bound": "mfma", "kernel": "cheb_step_pipe<float>" if prec == "f32" else
+        "roofline": {"bound": "mfma", "kernel": "cheb_step_mfma<float>" if prec == "f32" else
                      "cheb_step_bf16_pipe<float>", "achieved": round(2.0 * len(d) * cfg.n / launch_s / 1e12, 3),
                      "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                      "frac": round(2.0 * len(d) * cfg.n / launch_s / 1e12 / PEAK_TFLOPS[prec], 4),
@@ -313,8 +313,8 @@ def main():
         "hbm_gbs_algorithmic": round(alg_bytes_launch / launch_s / 1e9, 1),
         "issued_tflops": round(issued_flops_launch / launch_s / 1e12, 2),
         "issued_frac": round(issued_flops_launch / launch_s / 1e12 / peak, 4),
-        "roofline": {"bound": "mfma", "kernel": "cheb_step_pipe<double, 1>" if args.precision == "f64"
-                     else ("cheb_step_pipe<float, 1>" if args.precision == "f32"
+        "roofline": {"bound": "mfma", "kernel": "cheb_step_mfma<double>" if args.precision == "f64"
+                     else ("cheb_step_mfma<float>" if args.precision == "f32"
                            else "cheb_step_bf16_pipe<float>"),
                      "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic,

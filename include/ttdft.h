@@ -72,7 +72,11 @@ typedef struct {
   const int32_t *tile_rowptr;  /* device [n_block_rows+1]: tiles of block row B are
                                   tile_rowptr[B] .. tile_rowptr[B+1]-1                         */
   const int32_t *tile_col;     /* device [n_tiles]: block column of each tile, ascending in a row */
-  const void *vals;            /* device [n_tiles][64][64] row-major values, dtype below       */
+  const void *vals;            /* device [n_tiles*4096] values, dtype below, each tile in
+                                  matrix-core fragment order: entry (i, j) of tile t at
+                                  t*4096 + 64*(4*(j/4) + i/16) + 16*(j%4) + i%16 (the 16x4
+                                  sub-block of rows 16*(i/16).., columns 4*(j/4).. is 64
+                                  consecutive values, column-major inside)              */
   ttdft_dtype dtype;
   const uint64_t *frag_mask;   /* device [n_tiles] or NULL: bit (4*kk + mb) set when the 16x4
                                   sub-block rows 16mb..16mb+15, columns 4kk..4kk+3 of the tile
@@ -96,7 +100,8 @@ ttdft_status ttdft_bsr_plan(int32_t r, const int64_t *rowptr, const int32_t *col
  * Builds the lattice-blocked BSR arrays (all host buffers, caller-allocated
  * with the sizes from ttdft_bsr_plan):
  *   tile_rowptr[n_block_rows+1], tile_col[n_tiles],
- *   vals[n_tiles*4096] of dtype (F64, F32 or BF16; rounding to nearest even),
+ *   vals[n_tiles*4096] of dtype (F64, F32 or BF16; rounding to nearest even), in
+ *   the fragment order of ttdft_bsr.vals,
  *   perm[64*n_block_rows]: blocked row -> natural row, or -1 for a padding row,
  *   entry_slot[nnz] (may be NULL): flat index into vals of each CSR entry,
  *   mask[n_tiles*64] (may be NULL): bit j of word (t*64 + i) set when entry
@@ -290,14 +295,15 @@ size_t ttdft_cheb_filter_backward_workspace(const ttdft_bsr *H, int64_t n_vec, i
  *   Ybar_k = alpha_k (H - cI) Ybar_{k+1} - beta_{k+1} Ybar_{k+2}  (beta_m = 0),
  * and
  *   dX = Ybar_0  (= p(H) dY, H symmetric),
- *   dH[t][i][j] = sum_k alpha_k <Ybar_{k+1}[row i], Y_k[col j]>  for each stored
+ *   dH[t](i, j) = sum_k alpha_k <Ybar_{k+1}[row i], Y_k[col j]>  for each stored
  *   entry (i, j) of tile t: the derivative with respect to that entry with all
  *   entries independent (the derivative along a symmetric perturbation of the
  *   pair (i,j), (j,i) is the sum of the two).  Entries whose mask bit is clear
  *   are written as 0.
  * X, dY: device 64*n_block_rows x n_vec of x_dtype (ldx, lddy).  dX: same shape
  * and dtype (lddx), overlapping neither X, dY nor work.  dH_vals: device
- * [n_tiles][64][64], FP64 when x_dtype is F64 and FP32 otherwise.  mask: device
+ * [n_tiles*4096] in the layout of the tile values (fragment order), FP64 when
+ * x_dtype is F64 and FP32 otherwise.  mask: device
  * [n_tiles*64] from ttdft_bsr_build, or NULL (every tile entry written).  The
  * result does not depend on ckpt_every (bitwise).  ASYNC.
  * Errors: NULL, SHAPE, DTYPE, BOUNDS, DEGREE, ALIAS, WORKSPACE, HIP.

@@ -52,7 +52,7 @@ class BsrMatrix:
     n_tiles: int
     tile_rowptr: torch.Tensor
     tile_col: torch.Tensor
-    vals: torch.Tensor          # [n_tiles, 64, 64] (bf16 held as torch.bfloat16)
+    vals: torch.Tensor          # [n_tiles, 4096] in fragment order (bf16 held as torch.bfloat16)
     perm: torch.Tensor          # blocked row -> natural row or -1 (int64, device)
     inv_perm: torch.Tensor      # natural row -> blocked row (int64, device)
     entry_slot: np.ndarray      # host: flat vals index of each CSR entry
@@ -99,7 +99,7 @@ def bsr_build(indptr, indices, data, r: int, dtype=torch.float64, device="cuda")
     return BsrMatrix(r=r, N=N, n_block_rows=nbr, n_tiles=nt,
                      tile_rowptr=torch.from_numpy(tptr).to(device),
                      tile_col=torch.from_numpy(tcol).to(device),
-                     vals=tvals.reshape(nt, 64, 64).to(device),
+                     vals=tvals.reshape(nt, 4096).to(device),
                      perm=torch.from_numpy(perm).to(device),
                      inv_perm=torch.from_numpy(inv).to(device),
                      entry_slot=slot,
@@ -239,7 +239,7 @@ def cheb_filter_backward(H: BsrMatrix, X: torch.Tensor, dY: torch.Tensor, m: int
     n = X.shape[1]
     code = _code(X)
     dX = torch.empty_like(X)
-    dH = torch.empty((H.n_tiles, 64, 64), dtype=torch.float64 if code == F64 else torch.float32,
+    dH = torch.empty((H.n_tiles, 4096), dtype=torch.float64 if code == F64 else torch.float32,
                      device=X.device)
     need = _lib.load().ttdft_cheb_filter_backward_workspace(C.byref(hs), n, m, ckpt_every, code)
     w = _work(need, X.device)
@@ -282,8 +282,8 @@ def bsr_astype(H: BsrMatrix, dtype: torch.dtype) -> BsrMatrix:
     code = DTYPE_CODES[dtype]
     if code == H.dtype:
         return H
-    flat = H.vals.reshape(H.n_tiles * 64, 64)
-    vals = cast(flat, dtype).reshape(H.n_tiles, 64, 64)
+    flat = H.vals.reshape(H.n_tiles * 64, 64)      # elementwise: the layout is the same for every dtype
+    vals = cast(flat, dtype).reshape(H.n_tiles, 4096)
     return BsrMatrix(r=H.r, N=H.N, n_block_rows=H.n_block_rows, n_tiles=H.n_tiles,
                      tile_rowptr=H.tile_rowptr, tile_col=H.tile_col, vals=vals, perm=H.perm,
                      inv_perm=H.inv_perm, entry_slot=H.entry_slot, mask=H.mask, dtype=code,

@@ -249,7 +249,8 @@ ttdft_status ttdft_bsr_build(int32_t r, const int64_t *rowptr, const int32_t *co
       L.split(col[p], bc, lc);
       const int32_t *first = tile_col + tptr[b], *last = tile_col + tptr[b + 1];
       const int64_t t = tptr[b] + (std::lower_bound(first, last, (int32_t)bc) - first);
-      const int64_t slot = t * kTileElems + l * 64 + lc;
+      // fragment order: the 16x4 fragment (lc/4, l/16) is 64 consecutive values
+      const int64_t slot = t * kTileElems + 64 * (4 * (lc >> 2) + (l >> 4)) + 16 * (lc & 3) + (l & 15);
       if (dtype == TTDFT_F64) {
         ((double *)vals)[slot] = val[p];
       } else if (dtype == TTDFT_F32) {

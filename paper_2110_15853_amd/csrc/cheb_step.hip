@@ -11,8 +11,14 @@
 // Work decomposition: one work-group owns one block row B and one column tile
 // of vectors and walks the (at most 27) tiles of B, accumulating in matrix-core
 // registers.  Each output element is produced by exactly one work-group, so
-// results are deterministic (no atomics).  FP64 and FP32 use the pipelined
-// kernel cheb_step_pipe<T>; BF16 tiles use the LDS-staged 16x16x32 bf16 kernel.
+// results are deterministic (no atomics).  FP64 and FP32 tiles use
+// cheb_step_mfma<T> (16x16x4 ops, tiles moved to LDS by LDS-DMA); BF16 tiles
+// use cheb_step_bf16_pipe (16x16x32 bf16 ops).
+//
+// Tile values are stored in matrix-core fragment order: element (i, j) of a
+// tile at 64*(4*(j/4) + i/16) + 16*(j%4) + i%16, i.e. the 16x4 fragment
+// (kk = j/4, mb = i/16) is 64 consecutive values and lane l of the 16x16x4 op
+// takes value l of it as its A operand H[16mb + l%16][4kk + l/16].
 #include "ttdft_internal.h"
 
 namespace ttdft {
@@ -42,24 +48,13 @@ template <> struct Mfma4<float> {
   static __device__ inline int row(int lane, int t) { return 4 * (lane >> 4) + t; }
 };
 
-// Pipelined FP64 / FP32 path.  8 waves per work-group; the work-group owns block row B and
-// 128 vectors, wave w the 64 x 16 output slab of vectors 16w .. 16w+15.
-//  - A operand (H tile): double-buffered in LDS in matrix-core fragment order,
-//    element H[16*mb + (l & 15)][4*kk + (l >> 4)] of fragment (kk, mb) in its
-//    64-slot region (lanes rotated within groups of 16, see store_h); the next
-//    tile is fetched into registers while the current one is contracted (one
-//    barrier per tile).
-//  - B operand (Y_k panel): each wave reads its own 16 vectors straight from
-//    global memory into registers, a whole tile (16 k-steps) ahead of use.
-constexpr int F64_NV = 128, F64_THREADS = 512, F64_S = 65;   // fragment row stride (+1 pad)
+// Work-group shape shared by both kernels: 8 waves, 128 vectors per work-group,
+// wave w owning vectors 16w .. 16w+15 of the column tile.
+constexpr int F64_NV = 128, F64_THREADS = 512;
 // launch order: column groups of ORDER_CGROUP tiles outermost; each XCD takes runs
 // of ORDER_CHUNK consecutive block rows (all column tiles of the group), the 8
 // XCDs working on neighbouring runs at the same time
 constexpr int ORDER_CGROUP = 16, ORDER_CHUNK = 1;
-// column blocks of 16 vectors per wave in the FP64 / FP32 kernel
-constexpr int PIPE_CB_F64 = 1, PIPE_CB_F32 = 1;
-// waves per SIMD the kernel is compiled for (register budget 512 / waves)
-template <typename T, int CB> constexpr int pipe_waves() { return (sizeof(T) == 8 && CB > 1) ? 2 : 4; }
 
 __device__ inline int64_t group_order(int64_t g, int64_t G, int64_t C) {
   // hardware ids go round-robin over 8 XCDs; give each XCD C consecutive logical
@@ -70,167 +65,158 @@ __device__ inline int64_t group_order(int64_t g, int64_t G, int64_t C) {
   return (g / span) * span + (g % 8) * C + (g / 8) % C;
 }
 
-// T = double (f64 16x16x4) or float (f32 16x16x4, same operand layouts).
-// CB = column blocks of 16 vectors per wave: the work-group covers 8*16*CB
-// vectors and each A fragment read from LDS feeds CB matrix-core ops.
-template <typename T, int CB>
-__global__ __launch_bounds__(F64_THREADS, (pipe_waves<T, CB>())) void cheb_step_pipe(
+// ---------------------------------------------------------------------------
+// FP64 / FP32 step kernel (T = double: f64 16x16x4 ops; T = float: f32 16x16x4,
+// same operand layouts).  Wave w computes the 64 x 16 output slab of vectors
+// 16w .. 16w+15 with four 16x16 accumulators.
+//  - A operand (H tile): the tile, already in fragment order in memory, is
+//    copied to LDS by contiguous 1 KB global_load_lds_dwordx4 transfers (16 bytes
+//    per lane, placed at base + 16*lane) without passing through registers; each
+//    A read is 64 consecutive values (no bank conflicts, no padding).  Two LDS
+//    buffers: the next tile's transfer is issued when the current tile's
+//    contraction starts and waited for only before the barrier that ends it.
+//  - B operand (Y_k panel): each wave reads its own 16 vectors straight from
+//    global memory into registers, a whole tile (16 k-steps) ahead of use.
+//  - all-zero 16x4 fragments (clear bits of the fragment mask) are skipped.
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// s_waitcnt vmcnt(N), other counters not waited for (gfx9 encoding)
+template <int N> __device__ inline void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+template <typename T>
+__global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_mfma(
     const int32_t *__restrict__ rowptr, const int32_t *__restrict__ tcol,
     const T *__restrict__ vals, const T *__restrict__ Yk, int64_t ldk,
     const T *__restrict__ Yp, int64_t ldp, T *Yo, int64_t ldo, int64_t n_vec,
     int64_t n_ct, int64_t n_block_rows, int64_t cgroup, int64_t n_wg, T alpha, T c,
     T beta, const uint64_t *__restrict__ frag_mask) {
   using M = Mfma4<T>;
-  constexpr int NVW = 16 * CB;            // vectors per wave
-  __shared__ T sH[2][16 * 4 * F64_S];
+  constexpr int PER_LANE = 16 / sizeof(T);                 // values per lane per transfer
+  constexpr int XFERS = kTileElems / (64 * PER_LANE) / 8;  // transfers per wave per tile
+  __shared__ __attribute__((aligned(16))) T sH0[kTileElems];
+  __shared__ __attribute__((aligned(16))) T sH1[kTileElems];
   const int64_t L = group_order(blockIdx.x, n_wg, cgroup * ORDER_CHUNK);
-  // logical id -> (column group, block row, column tile inside the group)
   const int64_t per_group = n_block_rows * cgroup;
   const int64_t cg = L / per_group, rem = L % per_group;
   const int64_t B = rem / cgroup;
   const int64_t ct = cg * cgroup + rem % cgroup;
-  if (ct >= n_ct) return;        // last group may be partial (whole work-group exits)
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t col0 = ct * (8 * NVW) + NVW * w + (lane & 15);   // column of block cb: col0 + 16 cb
-  const int krow = lane >> 4;    // row of the 4-row k-step this lane loads
+  if (ct >= n_ct) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t col0 = ct * F64_NV + 16 * w + (lane & 15);
+  // Columns past n_vec (last column tile) read a clamped, in-range column: an
+  // output column of the product depends only on its own B column, and those
+  // columns are never stored.  Every load is unconditional, which keeps the
+  // prefetch in flight (a per-lane guard makes the compiler wait on each load).
+  const int64_t colc = min(col0, n_vec - 1);
+  const int krow = lane >> 4;
 
-  typename M::acc_t acc[CB][4];
+  typename M::acc_t acc[4];
 #pragma unroll
-  for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[cb][j] = typename M::acc_t{0, 0, 0, 0};
-
+  for (int j = 0; j < 4; ++j) acc[j] = typename M::acc_t{0, 0, 0, 0};
   const int t_begin = rowptr[B], t_end = rowptr[B + 1];
-  T hreg[4], b0[CB][4], b1[CB][4];
 
-  // next H tile: half h (rows 32h .. 32h+31) into registers, then into LDS
-  auto load_h = [&](int t, int h) {
-    const T *Ht = vals + (int64_t)t * kTileElems + 2048 * h;
+  // The transfer is written as inline assembly: the compiler then neither orders
+  // it against the other loads nor makes barriers wait for every outstanding
+  // load on its behalf.  Completion is waited for explicitly (vmcnt counts it;
+  // waits the compiler places for other loads can only be stricter than needed).
+  auto dma_h = [&](int t, T *dst) {
+    const T *src = vals + (int64_t)t * kTileElems + (w * XFERS) * 64 * PER_LANE + PER_LANE * lane;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) hreg[q] = Ht[tid + F64_THREADS * q];
-  };
-  // Fragment lane l = i + 16j lives at slot 16j + ((i + j) mod 16) of its
-  // fragment: with the fragment stride of 65 this makes both the row-wise stores
-  // below and the fragment reads free of LDS bank conflicts.
-  auto store_h = [&](int buf, int h) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = 2048 * h + tid + F64_THREADS * q, r = idx >> 6, cc = idx & 63;
-      const int kk = cc >> 2, mb = r >> 4, j = cc & 3;
-      const int slot = 16 * j + (((r & 15) + j) & 15);
-      sH[buf][(kk * 4 + mb) * F64_S + slot] = hreg[q];
+    for (int q = 0; q < XFERS; ++q) {
+      const uint32_t lds = (uint32_t)(uintptr_t)(lds_void_t *)(dst + (w * XFERS + q) * 64 * PER_LANE);
+      asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                   :
+                   : "s"(__builtin_amdgcn_readfirstlane(lds)), "v"(src + q * 64 * PER_LANE)
+                   : "memory", "m0");
     }
   };
-  const int rd_slot = (lane & 48) + (((lane & 15) + (lane >> 4)) & 15);
-  // quarter qq (k-steps 4qq .. 4qq+3, panel rows 16qq .. 16qq+15) of the Y_k panel of tile t
-  // Columns past n_vec (last column tile) read a clamped, in-range column: an
-  // output column of the matrix-core product depends only on its own B column,
-  // and those columns are never stored.  Unconditional loads keep the prefetch
-  // asynchronous (a per-lane guard makes the compiler wait for each load).
-  int64_t colc[CB];
+  T b0[4], b1[4], b2[4], b3[4];
+  auto load_b = [&](int t, int qq, T (&dst)[4]) {
+    const T *Xp = Yk + ((int64_t)tcol[t] * 64 + 16 * qq + krow) * ldk + colc;
 #pragma unroll
-  for (int cb = 0; cb < CB; ++cb) colc[cb] = min(col0 + 16 * cb, n_vec - 1);
-  auto load_b = [&](int t, int qq, T (&dst)[CB][4]) {
-    const T *Xp = Yk + ((int64_t)tcol[t] * 64 + 16 * qq + krow) * ldk;
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) dst[cb][q] = Xp[(int64_t)(4 * q) * ldk + colc[cb]];
+    for (int q = 0; q < 4; ++q) dst[q] = Xp[(int64_t)(4 * q) * ldk];
   };
-  // all-zero 16x4 sub-blocks of the tile (bit clear in fm) are skipped; fm is
-  // uniform over the work-group, so the branch costs no divergence.  The four A
-  // fragments of a k-step are read from LDS before the branches so the reads are
-  // not serialised behind them.
-  auto mma_quarter = [&](const T *sA, int qq, const T (&bq)[CB][4], uint64_t fm) {
+  auto mma_quarter = [&](const T *sA, int qq, const T (&bq)[4], uint64_t fm) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int kk = 4 * qq + q;
       T a[4];
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb) a[mb] = sA[(kk * 4 + mb) * F64_S + rd_slot];
+      for (int mb = 0; mb < 4; ++mb) a[mb] = sA[(kk * 4 + mb) * 64 + lane];
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb)
-        if ((fm >> (kk * 4 + mb)) & 1ull) {
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) acc[cb][mb] = M::op(a[mb], bq[cb][q], acc[cb][mb]);
-        }
+        if ((fm >> (kk * 4 + mb)) & 1ull) acc[mb] = M::op(a[mb], bq[q], acc[mb]);
     }
   };
   auto tile_mask = [&](int t) -> uint64_t { return frag_mask ? frag_mask[t] : ~0ull; };
+  // one tile: contract `cur`, meanwhile move tile tn into `nxt` and its Y_k panel
+  // into b0..b3 (each quarter refilled once contracted)
+  auto step = [&](int t, const T *cur, T *nxt, uint64_t fm) {
+    const int tn = min(t + 1, t_end - 1);   // t may be t_end (empty step)
+    dma_h(tn, nxt);
+    mma_quarter(cur, 0, b0, fm);
+    load_b(tn, 0, b0);
+    mma_quarter(cur, 1, b1, fm);
+    load_b(tn, 1, b1);
+    mma_quarter(cur, 2, b2, fm);
+    load_b(tn, 2, b2);
+    mma_quarter(cur, 3, b3, fm);
+    load_b(tn, 3, b3);
+    wait_vmcnt<16>();      // this wave's transfers of tile tn are in LDS
+    __syncthreads();
+  };
 
-  // Software pipeline over the block row's tiles: while tile t is contracted from
-  // LDS buffer buf, tile t+1 is fetched into registers (H in two halves, stored to
-  // the other buffer; the Y_k panel in quarters, each refilled as soon as its
-  // quarter of tile t is done).  All loads are unconditional: on the last tile
-  // the "next" tile is the last tile again, so no value is undefined on any path
-  // and the compiler keeps the loads in flight instead of waiting on them.
   if (t_begin < t_end) {
-    T b2[CB][4], b3[CB][4];
+    dma_h(t_begin, sH0);
     load_b(t_begin, 0, b0);
     load_b(t_begin, 1, b1);
     load_b(t_begin, 2, b2);
     load_b(t_begin, 3, b3);
-    load_h(t_begin, 0);
-    store_h(0, 0);
-    load_h(t_begin, 1);
-    store_h(0, 1);
-    uint64_t fm = tile_mask(t_begin);
+    wait_vmcnt<16>();
     __syncthreads();
-    int buf = 0;
-    for (int t = t_begin; t < t_end; ++t) {
-      const int tn = min(t + 1, t_end - 1);
-      const uint64_t fm_next = tile_mask(tn);
-      const T *sA = sH[buf];
-      load_h(tn, 0);
-      mma_quarter(sA, 0, b0, fm);
-      load_b(tn, 0, b0);
-      store_h(buf ^ 1, 0);
-      mma_quarter(sA, 1, b1, fm);
-      load_b(tn, 1, b1);
-      load_h(tn, 1);
-      mma_quarter(sA, 2, b2, fm);
-      load_b(tn, 2, b2);
-      store_h(buf ^ 1, 1);
-      mma_quarter(sA, 3, b3, fm);
-      load_b(tn, 3, b3);
-      __syncthreads();
-      buf ^= 1;
-      fm = fm_next;
+    // tiles in pairs (the two LDS buffers stay distinct objects, so the compiler
+    // can tell the transfer into one from the reads of the other); an odd last
+    // tile is paired with an empty step (mask 0: no products)
+    uint64_t fm = tile_mask(t_begin);
+    for (int t = t_begin; t < t_end; t += 2) {
+      const uint64_t fm1 = t + 1 < t_end ? tile_mask(t + 1) : 0ull;
+      step(t, sH0, sH1, fm);
+      fm = t + 2 < t_end ? tile_mask(t + 2) : 0ull;
+      step(t + 1, sH1, sH0, fm1);
     }
   }
 
-  // epilogue: all loads of the 64 x 16 slab first, then the stores
+  // epilogue: loads first, then the stores
+  T yk[4][4], yp[4][4];
 #pragma unroll
-  for (int cb = 0; cb < CB; ++cb) {
-    const int64_t col = col0 + 16 * cb;
-    T yk[4][4], yp[4][4];
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      yk[mb][q] = Yk[(B * 64 + 16 * mb + M::row(lane, q)) * ldk + colc];
+  if (beta != T(0)) {
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        yk[mb][q] = Yk[(B * 64 + 16 * mb + M::row(lane, q)) * ldk + colc[cb]];
-    if (beta != T(0)) {
+        yp[mb][q] = Yp[(B * 64 + 16 * mb + M::row(lane, q)) * ldp + colc];
+  } else {
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
+    for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          yp[mb][q] = Yp[(B * 64 + 16 * mb + M::row(lane, q)) * ldp + colc[cb]];
-    } else {
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) yp[mb][q] = T(0);
-    }
-    if (col < n_vec) {
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int64_t grow = B * 64 + 16 * mb + M::row(lane, q);
-          Yo[grow * ldo + col] = alpha * (acc[cb][mb][q] - c * yk[mb][q]) - beta * yp[mb][q];
-        }
-    }
+      for (int q = 0; q < 4; ++q) yp[mb][q] = T(0);
   }
+  if (col0 >= n_vec) return;
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t grow = B * 64 + 16 * mb + M::row(lane, q);
+      Yo[grow * ldo + col0] = alpha * (acc[mb][q] - c * yk[mb][q]) - beta * yp[mb][q];
+    }
 }
 
 template <typename TX> __device__ inline float to_f32(TX v);
@@ -241,11 +227,12 @@ template <> __device__ inline float from_f32<float>(float v) { return v; }
 template <> __device__ inline __bf16 from_f32<__bf16>(float v) { return (__bf16)v; }
 
 // Pipelined BF16 path: BF16 H tiles, FP32 or BF16 iterates, FP32 accumulation
-// on the 16x16x32 bf16 op.  Same decomposition as cheb_step_pipe (8 waves,
+// on the 16x16x32 bf16 op.  Same decomposition as cheb_step_mfma (8 waves,
 // 128 vectors, wave w owns vectors 16w .. 16w+15):
-//  - A (H tile, 8 KB): double-buffered in LDS in fragment order, lane l of
-//    fragment (kk, mb) holding H[16mb + (l&15)][32kk + 8(l>>4) .. +7] as one
-//    16-byte read;
+//  - A (H tile, 8 KB): double-buffered in LDS in the 16x32 fragment order of
+//    the bf16 op, lane l of fragment (kk, mb) holding H[16mb + (l&15)][32kk +
+//    8(l>>4) .. +7] as one 16-byte read; each thread loads 16 bytes of the tile
+//    (8 rows of one column in the stored 16x4 fragment order) and scatters them;
 //  - B (Y_k): lane l gathers Y_k[32kk + 8(l>>4) + t][col], t = 0..7, rounds to
 //    bf16 and packs them; the next tile's values are fetched during the current
 //    tile's contraction.
@@ -267,7 +254,9 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_bf16_pipe(
   if (ct >= n_ct) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t col = ct * F64_NV + 16 * w + (lane & 15);
-  const bool col_ok = col < n_vec;
+  // columns past n_vec load a clamped in-range column (never stored; an output
+  // column depends only on its own B column), so every load is unconditional
+  const int64_t colc = min(col, n_vec - 1);
   const int kgrp = lane >> 4;
 
   v4f acc[4];
@@ -281,21 +270,25 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_bf16_pipe(
     hreg = *reinterpret_cast<const v8bf *>(vals + (int64_t)t * kTileElems + 8 * tid);
   };
   auto store_h = [&](int buf) {
-    const int r = tid >> 3, c8 = (tid & 7) * 8;          // row r, columns c8 .. c8+7
-    const int kk = c8 >> 5, g = (c8 & 31) >> 3, mb = r >> 4;
-    const int fl = (r & 15) + 16 * g;
-    *reinterpret_cast<v8bf *>(&sH[buf][((kk * 4 + mb) * 64 + fl) * 8]) = hreg;
+    // thread tid holds stored values 8 tid .. 8 tid + 7: fragment f = tid / 8 of
+    // the 16x4 order, its lanes fl0 .. fl0 + 7, i.e. rows i0 .. i0 + 7 of column j
+    const int f = tid >> 3, fl0 = (tid & 7) * 8;
+    const int i0 = 16 * (f & 3) + (fl0 & 15), j = 4 * (f >> 2) + (fl0 >> 4);
+    const int kk = j >> 5, g = (j & 31) >> 3, e = j & 7, mb = i0 >> 4;
+    __bf16 *dst = &sH[buf][((kk * 4 + mb) * 64 + (i0 & 15) + 16 * g) * 8 + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) dst[8 * u] = hreg[u];
   };
   // two register sets for the Y_k values: one being contracted, one being fetched
   TX bA[2][8], bB[2][8];
   auto load_b = [&](int t, TX (&dst)[2][8]) {
-    const TX *Xp = Yk + (int64_t)tcol[t] * 64 * ldk + col;
+    const TX *Xp = Yk + (int64_t)tcol[t] * 64 * ldk + colc;
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int kr = 32 * kk + 8 * kgrp + q;
-        dst[kk][q] = col_ok ? Xp[(int64_t)kr * ldk] : TX(0);
+        dst[kk][q] = Xp[(int64_t)kr * ldk];
       }
   };
   // sub-blocks 4*kk4 + mb, kk4 = 8kk .. 8kk+7, sit at bits 32kk + 4j + mb
@@ -313,15 +306,14 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_bf16_pipe(
       }
     }
   };
+  // the last tile fetches itself again as "next": no load is conditional
   auto step = [&](int t, int buf, const TX (&cur)[2][8], TX (&nxt)[2][8]) {
-    const bool more = t + 1 < t_end;
+    const int tn = min(t + 1, t_end - 1);
     const uint64_t fm = frag_mask ? frag_mask[t] : ~0ull;
-    if (more) {
-      load_h(t + 1);
-      load_b(t + 1, nxt);
-    }
+    load_h(tn);
+    load_b(tn, nxt);
     mma_tile(buf, fm, cur);
-    if (more) store_h(buf ^ 1);
+    store_h(buf ^ 1);
     __syncthreads();
   };
 
@@ -336,18 +328,33 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_bf16_pipe(
     if (t + 1 < t_end) step(t + 1, 1, bB, bA);
   }
 
-  if (!col_ok) return;
+  // epilogue: loads first, then the stores
+  float yk[4][4], yp[4][4];
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb) {
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      yk[mb][q] = to_f32<TX>(Yk[(B * 64 + 16 * mb + 4 * (lane >> 4) + q) * ldk + colc]);
+  if (beta != 0.0f) {
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        yp[mb][q] = to_f32<TX>(Yp[(B * 64 + 16 * mb + 4 * (lane >> 4) + q) * ldp + colc]);
+  } else {
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) yp[mb][q] = 0.0f;
+  }
+  if (col >= n_vec) return;
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int64_t grow = B * 64 + 16 * mb + 4 * (lane >> 4) + q;
-      const float y = to_f32<TX>(Yk[grow * ldk + col]);
-      float out = alpha * (acc[mb][q] - c * y);
-      if (beta != 0.0f) out -= beta * to_f32<TX>(Yp[grow * ldp + col]);
-      Yo[grow * ldo + col] = from_f32<TX>(out);
+      Yo[grow * ldo + col] = from_f32<TX>(alpha * (acc[mb][q] - c * yk[mb][q]) - beta * yp[mb][q]);
     }
-  }
 }
 
 }  // namespace
@@ -356,20 +363,19 @@ hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, con
                             int64_t ldp, void *Yo, int64_t ldo, int64_t n_vec, double alpha,
                             double c, double beta, ttdft_dtype xt, hipStream_t s) {
   if (H.dtype == TTDFT_F64 || H.dtype == TTDFT_F32) {
-    const int cb = H.dtype == TTDFT_F64 ? PIPE_CB_F64 : PIPE_CB_F32;
-    const int64_t ctp = (n_vec + 128 * cb - 1) / (128 * cb);
+    const int64_t ctp = (n_vec + F64_NV - 1) / F64_NV;
     const int64_t cgroup = std::min<int64_t>(ctp, ORDER_CGROUP);
     const int64_t n_groups = (ctp + cgroup - 1) / cgroup;
     const int64_t wg = n_groups * H.n_block_rows * cgroup;
     if (wg > 0x7fffffff) return hipErrorInvalidConfiguration;
     if (H.dtype == TTDFT_F64)
-      hipLaunchKernelGGL((cheb_step_pipe<double, PIPE_CB_F64>), dim3((unsigned)wg), dim3(F64_THREADS),
-                         0, s, H.tile_rowptr, H.tile_col, (const double *)H.vals, (const double *)Yk,
+      hipLaunchKernelGGL(cheb_step_mfma<double>, dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
+                         H.tile_rowptr, H.tile_col, (const double *)H.vals, (const double *)Yk,
                          ldk, (const double *)Yp, ldp, (double *)Yo, ldo, n_vec, ctp,
                          H.n_block_rows, cgroup, wg, alpha, c, beta, H.frag_mask);
     else
-      hipLaunchKernelGGL((cheb_step_pipe<float, PIPE_CB_F32>), dim3((unsigned)wg), dim3(F64_THREADS),
-                         0, s, H.tile_rowptr, H.tile_col, (const float *)H.vals, (const float *)Yk,
+      hipLaunchKernelGGL(cheb_step_mfma<float>, dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
+                         H.tile_rowptr, H.tile_col, (const float *)H.vals, (const float *)Yk,
                          ldk, (const float *)Yp, ldp, (float *)Yo, ldo, n_vec, ctp,
                          H.n_block_rows, cgroup, wg, (float)alpha, (float)c, (float)beta,
                          H.frag_mask);

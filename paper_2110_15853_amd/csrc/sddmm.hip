@@ -1,8 +1,9 @@
 // Sampled dense-dense product on the tile pattern of H, for the gradient of the
 // Chebyshev filter with respect to the stored entries of H:
-//     dH[t][i][j] (+)= coef * sum_c Abar[64*B + i][c] * Yk[64*B' + j][c]
+//     dH[t](i, j) (+)= coef * sum_c Abar[64*B + i][c] * Yk[64*B' + j][c]
 // for every stored tile t = (B, B'), entries outside the true pattern (mask bit
-// clear) written as 0.  One work-group owns one tile and sweeps the vector
+// clear) written as 0.  dH has the layout of the tile values (fragment order:
+// entry (i, j) at 64*(4*(j/4) + i/16) + 16*(j%4) + i%16).  One work-group owns one tile and sweeps the vector
 // dimension in 32-wide panels, both operands staged transposed in LDS
 // ([vector][row]) so every matrix-core operand read is 16 consecutive values.
 // FP64 inputs use the f64 16x16x4 op; FP32 and BF16 inputs accumulate in FP32
@@ -94,9 +95,10 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
     for (int q = 0; q < 4; ++q) {
       const int i = 16 * w + O::row(lane, q);
       const bool on = mask ? ((mask[t * 64 + i] >> j) & 1ull) != 0 : true;
+      const int pos = 64 * (4 * (j >> 2) + (i >> 4)) + 16 * (j & 3) + (i & 15);   // fragment order
       TC v = coef * acc[jb][q];
-      if (accumulate) v += out[i * 64 + j];
-      out[i * 64 + j] = on ? v : TC(0);
+      if (accumulate) v += out[pos];
+      out[pos] = on ? v : TC(0);
     }
   }
 }

@@ -125,10 +125,14 @@ def test_bsr_builder_roundtrip(lib_built, r, h):
     assert nbr == nb ** 3 and tptr[-1] == nt
     Hd = oracle.csr_from_arrays(ip, ix, d, N).toarray()
     dense = np.zeros((nbr * 64, nbr * 64))
+    # documented tile layout (fragment order): entry (i, j) at 64*(4*(j/4) + i/16) + 16*(j%4) + i%16
+    ii, jj = np.meshgrid(np.arange(64), np.arange(64), indexing="ij")
+    pos = 64 * (4 * (jj // 4) + ii // 16) + 16 * (jj % 4) + ii % 16
+    assert sorted(pos.ravel()) == list(range(4096))
     for B in range(nbr):
         assert np.all(np.diff(tcol[tptr[B]:tptr[B + 1]]) > 0)
         for t in range(tptr[B], tptr[B + 1]):
-            dense[B * 64:(B + 1) * 64, tcol[t] * 64:(tcol[t] + 1) * 64] = vals[t * 4096:(t + 1) * 4096].reshape(64, 64)
+            dense[B * 64:(B + 1) * 64, tcol[t] * 64:(tcol[t] + 1) * 64] = vals[t * 4096:(t + 1) * 4096][pos]
     real = perm >= 0
     assert real.sum() == N and sorted(perm[real]) == list(range(N))
     back = np.zeros((N, N))
@@ -136,9 +140,10 @@ def test_bsr_builder_roundtrip(lib_built, r, h):
     np.testing.assert_array_equal(back, Hd)            # bitwise
     assert not dense[~real].any() and not dense[:, ~real].any()
     np.testing.assert_array_equal(vals[slot], d)
-    # mask marks exactly the stored entries
-    bits = np.zeros(nt * 4096, bool)
-    bits[slot] = True
+    # mask marks exactly the stored entries (bits in row-major (i, j) of each tile)
+    stored = np.zeros(nt * 4096, bool)
+    stored[slot] = True
+    bits = stored.reshape(nt, 4096)[:, pos.ravel()].reshape(-1)
     weights = (np.uint64(1) << np.arange(64, dtype=np.uint64))
     words = (bits.reshape(nt * 64, 64).astype(np.uint64) * weights).sum(axis=1, dtype=np.uint64)
     np.testing.assert_array_equal(words, mask)
