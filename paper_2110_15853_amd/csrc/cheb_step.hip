@@ -86,6 +86,17 @@ template <int N> __device__ inline void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
 }
 
+// raw buffer load of one value (descriptor word 3 of the gfx9 family: 32-bit
+// data, no swizzle); voffset per lane, soffset wave-uniform, both in bytes
+constexpr int kBufferWord3 = 0x00020000;
+template <typename T> __device__ inline T buffer_load(__amdgpu_buffer_rsrc_t rs, int32_t voff, int32_t soff);
+template <> __device__ inline double buffer_load<double>(__amdgpu_buffer_rsrc_t rs, int32_t voff, int32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+}
+template <> __device__ inline float buffer_load<float>(__amdgpu_buffer_rsrc_t rs, int32_t voff, int32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+}
+
 template <typename T>
 __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_mfma(
     const int32_t *__restrict__ rowptr, const int32_t *__restrict__ tcol,
@@ -135,22 +146,33 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_mfma(
     }
   };
   T b0[4], b1[4], b2[4], b3[4];
+  // Y_k loads are raw buffer loads: the descriptor covers the 64-row panel of
+  // tile t (wave-uniform, scalar registers), the per-lane byte offset of row
+  // krow, column colc is one 32-bit register and the k-step row offset a scalar,
+  // so the 16 loads of a tile need no 64-bit address registers.  Reads past the
+  // descriptor's range would return 0 instead of faulting.
+  const int32_t yoff = (int32_t)(((int64_t)krow * ldk + colc) * (int64_t)sizeof(T));
+  const int32_t panel_bytes = (int32_t)(64 * ldk * (int64_t)sizeof(T));
   auto load_b = [&](int t, int qq, T (&dst)[4]) {
-    const T *Xp = Yk + ((int64_t)tcol[t] * 64 + 16 * qq + krow) * ldk + colc;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(Yk + (int64_t)tcol[t] * 64 * ldk), 0, panel_bytes, kBufferWord3);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) dst[q] = Xp[(int64_t)(4 * q) * ldk];
+    for (int q = 0; q < 4; ++q)
+      dst[q] = buffer_load<T>(rs, yoff, (int32_t)((16 * qq + 4 * q) * ldk * (int64_t)sizeof(T)));
   };
+  // the 16 A fragments of a quarter (4 k-steps) are read from LDS before its
+  // matrix-core ops, so the LDS latency is paid once per quarter
   auto mma_quarter = [&](const T *sA, int qq, const T (&bq)[4], uint64_t fm) {
+    T a[4][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kk = 4 * qq + q;
-      T a[4];
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb) a[mb] = sA[(kk * 4 + mb) * 64 + lane];
+      for (int mb = 0; mb < 4; ++mb) a[q][mb] = sA[((4 * qq + q) * 4 + mb) * 64 + lane];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb)
-        if ((fm >> (kk * 4 + mb)) & 1ull) acc[mb] = M::op(a[mb], bq[q], acc[mb]);
-    }
+        if ((fm >> ((4 * qq + q) * 4 + mb)) & 1ull) acc[mb] = M::op(a[q][mb], bq[q], acc[mb]);
   };
   auto tile_mask = [&](int t) -> uint64_t { return frag_mask ? frag_mask[t] : ~0ull; };
   // one tile: contract `cur`, meanwhile move tile tn into `nxt` and its Y_k panel
