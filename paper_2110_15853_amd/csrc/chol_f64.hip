@@ -5,10 +5,14 @@
 //     orthonormal columns.
 // The n x n problem is padded to np = 64*ceil(n/64) with an identity block so
 // every tile is a full 64x64 block.  Right-looking blocked factorisation with
-// 64-wide panels (one work-group factors the diagonal block in LDS and inverts
-// it; the panel below and the trailing lower triangle are updated tile by tile),
-// then L^{-1} by block forward substitution.  Breakdown (a non-positive or
-// non-finite pivot) sets *info and every later kernel returns immediately.
+// 64-wide panels (one wave factors the diagonal block and inverts it; the panel
+// below and the trailing lower triangle are updated tile by tile), then L^{-1}
+// by recursive doubling: with the inverses X11, X22 of two adjacent diagonal
+// ranges known, the coupling block of the inverse of [[L11, 0], [L21, L22]] is
+// X21 = -X22 (L21 X11), formed for all pairs of a level by two batched
+// matrix-core products (ranges of 1, 2, 4, ... blocks).  Breakdown (a
+// non-positive or non-finite pivot) sets *info and the factorisation kernels
+// return immediately.
 #include "ttdft_internal.h"
 
 namespace ttdft {
@@ -70,64 +74,76 @@ __global__ void gram_scale_kernel(double *G, int64_t n, int64_t np, const double
   }
 }
 
-// factor the diagonal block p in LDS; write L_pp (lower) into G and L_pp^{-1} into X
-__global__ __launch_bounds__(256) void potrf_diag_kernel(double *G, int64_t np, int p, double *X,
-                                                         int *info) {
+// Factor the diagonal block p with one wave; write L_pp (lower) into G and
+// L_pp^{-1} into X.  The block sits in LDS row-major; step j (a rolled loop):
+// lane i > j forms l_ij = a_ij / sqrt(a_jj) in place, then for every k > j lane
+// i applies a_ik -= l_ij l_kj, l_kj read with the same address by every lane.  A single wave executes its LDS operations in order, so no barrier is
+// needed between the steps.  Then lane c holds column c of the identity in
+// registers and eliminates with the factor's columns: x_j = b_j / l_jj,
+// b_k -= l_kj x_j (k > j), leaving column c of L^{-1} (unrolled; a scheduling
+// barrier between steps bounds the register use).
+__global__ __launch_bounds__(64) void potrf_diag_kernel(double *G, int64_t np, int p, double *X,
+                                                        int *info) {
   if (*info) return;
-  __shared__ double a[T][T + 1];
-  __shared__ double inv[T][T + 1];
-  __shared__ int bad;
-  const int tid = threadIdx.x;
+  __shared__ double La[T][T + 1];
+  const int lane = threadIdx.x;
   double *Gp = G + (int64_t)p * T * np + (int64_t)p * T;
-  for (int q = 0; q < 16; ++q) {
-    const int idx = tid + 256 * q, r = idx >> 6, c = idx & 63;
-    a[r][c] = Gp[r * np + c];
-  }
-  if (tid == 0) bad = 0;
+  for (int r = 0; r < T; ++r) La[r][lane] = Gp[r * np + lane];   // coalesced rows
   __syncthreads();
+  int bad = 0;
   for (int j = 0; j < T; ++j) {
-    if (tid == 0) {
-      const double piv = a[j][j];
-      if (!(piv > 0.0) || !isfinite(piv)) {
-        bad = p * T + j + 1;
-        a[j][j] = 1.0;
-      } else {
-        a[j][j] = sqrt(piv);
+    double piv = La[j][j];                  // the same value in every lane
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      if (!bad) bad = p * T + j + 1;
+      piv = 1.0;
+    }
+    const double ljj = sqrt(piv);
+    double l = 0.0;
+    if (lane > j) {
+      l = La[lane][j] / ljj;
+      La[lane][j] = l;
+    }
+    if (lane == j) La[j][j] = ljj;
+    // trailing update in chunks of 8 columns: all reads of a chunk, then the
+    // products (kept only for columns k > j; entries above the diagonal are
+    // updated too but never read), then the writes -- one LDS round trip per
+    // chunk, no per-column branch
+    for (int kc = (j + 1) & ~7; kc < T; kc += 8) {
+      double lk[8], ak[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        lk[u] = La[kc + u][j];
+        ak[u] = La[lane][kc + u];
       }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double v = fma(-l, lk[u], ak[u]);
+        ak[u] = kc + u > j ? v : ak[u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) La[lane][kc + u] = ak[u];
     }
-    __syncthreads();
-    const double ljj = a[j][j];
-    if (tid > j && tid < T) a[tid][j] /= ljj;
-    __syncthreads();
-    // trailing update of the lower triangle: a[i][k] -= a[i][j] a[k][j], j < k <= i
-    for (int idx = tid; idx < T * T; idx += 256) {
-      const int i = idx >> 6, k = idx & 63;
-      if (k > j && i >= k) a[i][k] -= a[i][j] * a[k][j];
-    }
-    __syncthreads();
   }
+  __syncthreads();
   if (bad) {
-    if (tid == 0) atomicCAS(info, 0, bad);
+    if (lane == 0) atomicCAS(info, 0, bad);
     return;
   }
-  // inverse of the lower factor, one column per thread (forward substitution)
-  if (tid < T) {
-    const int c = tid;
-    for (int i = 0; i < T; ++i) inv[i][c] = 0.0;
-    inv[c][c] = 1.0 / a[c][c];
-    for (int i = c + 1; i < T; ++i) {
-      double s = 0.0;
-      for (int k = c; k < i; ++k) s += a[i][k] * inv[k][c];
-      inv[i][c] = -s / a[i][i];
-    }
+  double b[T];
+#pragma unroll
+  for (int k = 0; k < T; ++k) b[k] = k == lane ? 1.0 : 0.0;
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    const double x = b[j] / La[j][j];
+    b[j] = x;
+#pragma unroll
+    for (int k = j + 1; k < T; ++k) b[k] = fma(-La[k][j], x, b[k]);
+    __builtin_amdgcn_sched_barrier(0);
   }
-  __syncthreads();
   double *Xp = X + (int64_t)p * T * np + (int64_t)p * T;
-  for (int q = 0; q < 16; ++q) {
-    const int idx = tid + 256 * q, r = idx >> 6, c = idx & 63;
-    Gp[r * np + c] = (c <= r) ? a[r][c] : 0.0;
-    Xp[r * np + c] = inv[r][c];
-  }
+#pragma unroll
+  for (int i = 0; i < T; ++i) Xp[(int64_t)i * np + lane] = b[i];   // lane = column: coalesced
+  for (int r = 0; r < T; ++r) Gp[r * np + lane] = lane <= r ? La[r][lane] : 0.0;
 }
 
 // L_ip = A_ip L_pp^{-T} for every block row i > p (one work-group each)
@@ -165,37 +181,6 @@ __global__ __launch_bounds__(256) void syrk_update_kernel(double *G, int64_t np,
     for (int c = 0; c < 4; ++c) Aij[(4 * ty + r) * np + 4 * tx + c] -= acc[r][c];
 }
 
-// block row i of X = L^{-1}: X_ij = -L_ii^{-1} sum_{k=j}^{i-1} L_ik X_kj, all j < i
-__global__ __launch_bounds__(256) void trinv_row_kernel(const double *G, int64_t np, int i,
-                                                        double *X, const int *info) {
-  if (*info) return;
-  __shared__ double sA[T][T + 1], sB[T][T + 1];
-  const int j = blockIdx.x;
-  double s[4][4] = {};
-  for (int k = j; k < i; ++k)
-    tile_mac(G + (int64_t)i * T * np + (int64_t)k * T, np, false,
-             X + (int64_t)k * T * np + (int64_t)j * T, np, false, s, sA, sB);
-  // write S into LDS, then X_ij = -Linv_ii * S
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  __shared__ double sS[T][T + 1];
-  for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c) sS[4 * ty + r][4 * tx + c] = s[r][c];
-  __syncthreads();
-  double out[4][4] = {};
-  const double *Lii_inv = X + (int64_t)i * T * np + (int64_t)i * T;
-  for (int q = 0; q < 16; ++q) {
-    const int idx = threadIdx.x + 256 * q, r = idx >> 6, c = idx & 63;
-    sA[r][c] = Lii_inv[r * np + c];
-  }
-  __syncthreads();
-  for (int k = 0; k < T; ++k)
-    for (int r = 0; r < 4; ++r)
-      for (int c = 0; c < 4; ++c) out[r][c] = fma(sA[4 * ty + r][k], sS[k][4 * tx + c], out[r][c]);
-  double *Xij = X + (int64_t)i * T * np + (int64_t)j * T;
-  for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c) Xij[(4 * ty + r) * np + 4 * tx + c] = -out[r][c];
-}
-
 // M[i][j] = X[j][i] / d_i for i <= j, 0 below the diagonal (M = D^{-1} L^{-T})
 __global__ void form_m_kernel(const double *X, const double *d, int64_t np, double *M,
                               const int *info) {
@@ -214,9 +199,20 @@ inline unsigned grid_for(int64_t work) {
 
 }  // namespace
 
+// largest product block W = L21 X11 of the doubling levels (doubles)
+static size_t doubling_w_doubles(int nb) {
+  size_t w = 0;
+  for (int s = 1; s < nb; s *= 2) {
+    const int full = nb / (2 * s), mid = 2 * s * full + s;
+    w = std::max(w, (size_t)full * (size_t)(s * T) * (size_t)(s * T));
+    if (mid < nb) w = std::max(w, (size_t)((nb - mid) * T) * (size_t)(s * T));
+  }
+  return w;
+}
+
 size_t chol_rinv_scratch_doubles(int64_t n) {
   const int64_t np = (n + T - 1) / T * T;
-  return (size_t)np * np + (size_t)np;   // X = L^{-1} and d
+  return (size_t)np * np + (size_t)np + doubling_w_doubles((int)(np / T));   // X, d, W
 }
 
 // G: np x np (np = padded n, ld np) holding Y^T Y in its n x n part; Rinv: np x np.
@@ -224,19 +220,38 @@ hipError_t launch_chol_rinv(double *G, int64_t n, double *Rinv, double *scratch,
                             hipStream_t s, double shift) {
   const int64_t np = (n + T - 1) / T * T;
   const int nb = (int)(np / T);
-  double *X = scratch, *d = scratch + np * np;
+  double *X = scratch, *d = scratch + np * np, *W = d + np;
   hipLaunchKernelGGL(gram_scale_diag_kernel, dim3(grid_for(np)), dim3(256), 0, s, G, n, np, d, info);
   hipLaunchKernelGGL(gram_scale_kernel, dim3(grid_for(np * np)), dim3(256), 0, s, G, n, np, d, X, shift);
   for (int p = 0; p < nb; ++p) {
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, G, np, p, X, info);
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(64), 0, s, G, np, p, X, info);
     if (p + 1 < nb) {
       hipLaunchKernelGGL(trsm_panel_kernel, dim3(nb - p - 1), dim3(256), 0, s, G, np, p, X, info);
       const int pairs = (nb - p - 1) * (nb - p) / 2;
       hipLaunchKernelGGL(syrk_update_kernel, dim3(pairs), dim3(256), 0, s, G, np, p, nb, info);
     }
   }
-  for (int i = 1; i < nb; ++i)
-    hipLaunchKernelGGL(trinv_row_kernel, dim3(i), dim3(256), 0, s, G, np, i, X, info);
+  // L^{-1} by doubling: after level s every aligned range of 2s blocks is inverted
+  hipError_t e;
+  for (int sb = 1; sb < nb; sb *= 2) {
+    const int64_t S = (int64_t)sb * T, step = 2 * S * np + 2 * S;   // pair stride (elements)
+    const int full = nb / (2 * sb);
+    if (full > 0) {
+      // W_b = L21_b X11_b, then X21_b = -X22_b W_b
+      if ((e = launch_gemm_nn_batched(G + S * np, np, step, X, np, step, S, S, S, 1.0, W, S, S * S,
+                                      full, s)) != hipSuccess) return e;
+      if ((e = launch_gemm_nn_batched(X + S * np + S, np, step, W, S, S * S, S, S, S, -1.0,
+                                      X + S * np, np, step, full, s)) != hipSuccess) return e;
+    }
+    const int64_t lo = 2 * (int64_t)sb * full, mid = lo + sb;     // a shorter last pair
+    if (mid < nb) {
+      const int64_t S2 = (nb - mid) * T, L0 = lo * T, M0 = mid * T;
+      if ((e = launch_gemm_nn_batched(G + M0 * np + L0, np, 0, X + L0 * np + L0, np, 0, S2, S, S,
+                                      1.0, W, S, 0, 1, s)) != hipSuccess) return e;
+      if ((e = launch_gemm_nn_batched(X + M0 * np + M0, np, 0, W, S, 0, S2, S2, S, -1.0,
+                                      X + M0 * np + L0, np, 0, 1, s)) != hipSuccess) return e;
+    }
+  }
   hipLaunchKernelGGL(form_m_kernel, dim3(grid_for(np * np)), dim3(256), 0, s, X, d, np, Rinv, info);
   return hipGetLastError();
 }

@@ -184,9 +184,13 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(const double *__rest
 __global__ __launch_bounds__(THREADS, 2) void gemm_nn_kernel(
     const double *__restrict__ A, int64_t lda, const double *__restrict__ B, int64_t ldb,
     int64_t rows, int64_t K, int64_t N, double alpha, double *__restrict__ C, int64_t ldc,
-    int upper, int tiles_n, int64_t n_wg, int accumulate) {
+    int upper, int tiles_n, int64_t n_wg, int accumulate, int64_t stride_a, int64_t stride_b,
+    int64_t stride_c) {
   __shared__ double sA[2][BK][LDS_LD];
   __shared__ double sB[2][BK][LDS_LD];
+  A += (int64_t)blockIdx.y * stride_a;     // batch (grid.y) of equally shaped products
+  B += (int64_t)blockIdx.y * stride_b;
+  C += (int64_t)blockIdx.y * stride_c;
   const int64_t L = xcd_group(blockIdx.x, n_wg, tiles_n);
   const int64_t tn = L % tiles_n, tm = L / tiles_n;
   const int64_t i0 = tm * BM, j0 = tn * BN;
@@ -340,7 +344,20 @@ hipError_t launch_gemm_nn_ex(const double *A, int64_t lda, const double *B, int6
   const int64_t g = tiles_m * tiles_n;
   if (g > 0x7fffffff) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(gemm_nn_kernel, dim3((unsigned)g), dim3(THREADS), 0, s, A, lda, B, ldb,
-                     rows, K, N, alpha, C, ldc, upper ? 1 : 0, tiles_n, g, 0);
+                     rows, K, N, alpha, C, ldc, upper ? 1 : 0, tiles_n, g, 0, 0, 0, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_nn_batched(const double *A, int64_t lda, int64_t stride_a, const double *B,
+                                  int64_t ldb, int64_t stride_b, int64_t rows, int64_t K, int64_t N,
+                                  double alpha, double *C, int64_t ldc, int64_t stride_c, int batch,
+                                  hipStream_t s) {
+  if (rows <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  const int tiles_n = (int)((N + BN - 1) / BN);
+  const int64_t g = ((rows + BM - 1) / BM) * tiles_n;
+  if (g > 0x7fffffff || batch > 65535) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(gemm_nn_kernel, dim3((unsigned)g, (unsigned)batch), dim3(THREADS), 0, s, A, lda,
+                     B, ldb, rows, K, N, alpha, C, ldc, 0, tiles_n, g, 0, stride_a, stride_b, stride_c);
   return hipGetLastError();
 }
 
@@ -352,7 +369,7 @@ hipError_t launch_gemm_nn_acc(const double *A, int64_t lda, const double *B, int
   const int64_t g = ((rows + BM - 1) / BM) * tiles_n;
   if (g > 0x7fffffff) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(gemm_nn_kernel, dim3((unsigned)g), dim3(THREADS), 0, s, A, lda, B, ldb,
-                     rows, K, N, alpha, C, ldc, 0, tiles_n, g, 1);
+                     rows, K, N, alpha, C, ldc, 0, tiles_n, g, 1, 0, 0, 0);
   return hipGetLastError();
 }
 

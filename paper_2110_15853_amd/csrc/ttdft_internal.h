@@ -55,6 +55,11 @@ hipError_t launch_gemm_nn_ex(const double *A, int64_t lda, const double *B, int6
                              int64_t rows, int64_t K, int64_t N, double alpha, double *C,
                              int64_t ldc, bool upper, hipStream_t s);
 hipError_t launch_clear_ints(int *p, int count, hipStream_t s);
+// batch of C_b = alpha * A_b B_b (rows x K times K x N), A_b = A + b*stride_a etc.
+hipError_t launch_gemm_nn_batched(const double *A, int64_t lda, int64_t stride_a, const double *B,
+                                  int64_t ldb, int64_t stride_b, int64_t rows, int64_t K, int64_t N,
+                                  double alpha, double *C, int64_t ldc, int64_t stride_c, int batch,
+                                  hipStream_t s);
 // C[rows x N] += alpha * A[rows x K] B[K x N]
 hipError_t launch_gemm_nn_acc(const double *A, int64_t lda, const double *B, int64_t ldb,
                               int64_t rows, int64_t K, int64_t N, double alpha, double *C,

@@ -36,8 +36,11 @@ U32, U16 = 2.0 ** -24, 2.0 ** -8
 @pytest.mark.parametrize("hname,xname,r,n,m,tol", [
     ("f32", "f32", 20, 64, 10, 4 * 10 * U32),
     ("f32", "f32", 9, 130, 20, 4 * 20 * U32),
+    ("f32", "f32", 5, 1, 3, 4 * 3 * U32),          # one vector: 15 clamped lanes per wave
     ("bf16", "f32", 20, 64, 10, 2.5 * U16),
     ("bf16", "bf16", 20, 64, 10, 2.5 * U16),
+    ("bf16", "f32", 9, 130, 7, 2.5 * U16),         # ragged last column tile
+    ("bf16", "bf16", 6, 37, 5, 2.5 * U16),         # padded lattice, ragged columns
 ])
 def test_low_precision_filter_vs_oracle(hname, xname, r, n, m, tol):
     torch, P = require_gpu()
