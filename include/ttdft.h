@@ -277,6 +277,37 @@ ttdft_status ttdft_lanczos_upper_bound(const ttdft_bsr *H, const int64_t *perm, 
                                        uint64_t seed, double *bound, void *work,
                                        size_t work_bytes, void *stream);
 
+/*
+ * The same k Lanczos steps, returning both ends: bounds[0..2] as bound[0..2]
+ * above and bounds[3] = theta_min, the smallest eigenvalue of the Lanczos
+ * tridiagonal (an upper estimate of the bottom of the spectrum; the first pass
+ * of the subspace iteration takes its scaling point a0 and its cut a from it
+ * and the upper estimate).  bounds: host double[4].  Synchronises the stream.
+ * Workspace: ttdft_lanczos_workspace.  Errors: as ttdft_lanczos_upper_bound.
+ */
+ttdft_status ttdft_lanczos_bounds(const ttdft_bsr *H, const int64_t *perm, int32_t k,
+                                  uint64_t seed, double *bounds, void *work, size_t work_bytes,
+                                  void *stream);
+
+/* ---------------------------------------------------------------- convergence test */
+
+/* Bytes of workspace ttdft_ritz_residuals needs. */
+size_t ttdft_ritz_residuals_workspace(const ttdft_bsr *H, int64_t n_vec);
+
+/*
+ * Ritz residual norms res[j] = || H psi_j - lambda_j psi_j ||_2 of the output of
+ * steps 2-5 of Algorithm 1 (Sec. 3.4): the subspace iteration is repeated from
+ * Psi until they are small enough.  H must be FP64.  Psi: device FP64
+ * 64*n_block_rows x n_vec (ldp, blocked row order, zero padding rows);
+ * lambda: device FP64 [n_vec]; res: device FP64 [n_vec].  None of them may
+ * overlap the workspace or each other (res vs Psi, lambda).  Deterministic
+ * (fixed-order reductions).  ASYNC.
+ * Errors: NULL, SHAPE, DTYPE, WORKSPACE, ALIAS, HIP.
+ */
+ttdft_status ttdft_ritz_residuals(const ttdft_bsr *H, const double *Psi, int64_t ldp,
+                                  const double *lambda, int64_t n_vec, double *res, void *work,
+                                  size_t work_bytes, void *stream);
+
 /* ---------------------------------------------------------------- adjoint of step 1 */
 
 /*

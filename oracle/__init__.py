@@ -22,4 +22,6 @@ from .chfsi import (  # noqa: F401
     rayleigh_ritz,
     dense_eigh,
     csr_from_arrays,
+    ritz_residuals,
+    chfsi,
 )

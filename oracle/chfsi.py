@@ -178,3 +178,24 @@ def rayleigh_ritz(H, Y):
     HF = XF.T @ (H @ XF)
     lam, Q = dense_eigh(HF)
     return lam, XF @ Q
+
+
+def ritz_residuals(H, Psi, lam):
+    """Residual norms || H psi_j - lambda_j psi_j ||_2 of Ritz pairs, the
+    convergence test of the subspace iteration (Sec. 3.4): the definition,
+    column by column."""
+    R = H @ Psi - Psi * np.asarray(lam)[None, :]
+    return np.sqrt(np.sum(R * R, axis=0))
+
+
+def chfsi(H, X, m: int, a: float, b: float, a0: float, passes: int):
+    """Algorithm 1 applied `passes` times (Sec. 3.4): each pass filters the
+    previous Ritz vectors; after a pass the scaling point a0 and the cut a move
+    to the smallest and largest Ritz values (b is kept).  Returns (Lambda, Psi,
+    residual norms of the last pass)."""
+    lam = Psi = None
+    for _ in range(passes):
+        lam, Psi = rayleigh_ritz(H, cheb_filter(H, X, m, a, b, a0))
+        a0, a = float(lam.min()), float(lam.max())
+        X = Psi
+    return lam, Psi, ritz_residuals(H, Psi, lam)

@@ -23,6 +23,9 @@ from .api import (  # noqa: F401
     cheb_filter_backward,
     cholqr2,
     lanczos_upper_bound,
+    lanczos_bounds,
+    ritz_residuals,
+    chfsi_solve,
     gather_rows,
     project,
     rayleigh_ritz,

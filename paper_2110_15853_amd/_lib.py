@@ -60,6 +60,9 @@ SIGNATURES = {
                                           _I32, _P, _I64, _P, _P, _P, _SZ, _P]),
     "ttdft_lanczos_workspace": (_SZ, [_BSRP, _I32]),
     "ttdft_lanczos_upper_bound": (_INT, [_BSRP, _P, _I32, C.c_uint64, _P, _P, _SZ, _P]),
+    "ttdft_lanczos_bounds": (_INT, [_BSRP, _P, _I32, C.c_uint64, _P, _P, _SZ, _P]),
+    "ttdft_ritz_residuals_workspace": (_SZ, [_BSRP, _I64]),
+    "ttdft_ritz_residuals": (_INT, [_BSRP, _P, _I64, _P, _I64, _P, _P, _SZ, _P]),
     "ttdft_status_string": (C.c_char_p, [_INT]),
     "ttdft_last_error": (C.c_char_p, []),
     "ttdft_version": (C.c_char_p, []),

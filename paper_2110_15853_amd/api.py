@@ -318,3 +318,112 @@ def lanczos_upper_bound(H: BsrMatrix, k: int = 20, seed: int = 0):
     _lib.call("ttdft_lanczos_upper_bound", C.byref(hs), _ptr(H.perm), k, seed, out, _ptr(w),
               w.numel(), _stream())
     return float(out[0]), float(out[1]), float(out[2])
+
+
+def lanczos_bounds(H: BsrMatrix, k: int = 20, seed: int = 0):
+    """ttdft_lanczos_bounds: (theta_max, theta_max + Ritz residual,
+    theta_max + beta_{k+1}, theta_min) for an FP64 H."""
+    hs = H.c_struct()
+    out = (C.c_double * 4)()
+    w = _work(_lib.load().ttdft_lanczos_workspace(C.byref(hs), k), H.vals.device)
+    _lib.call("ttdft_lanczos_bounds", C.byref(hs), _ptr(H.perm), k, seed, out, _ptr(w),
+              w.numel(), _stream())
+    return float(out[0]), float(out[1]), float(out[2]), float(out[3])
+
+
+def ritz_residuals(H: BsrMatrix, Psi: torch.Tensor, lam: torch.Tensor,
+                   work: torch.Tensor = None) -> torch.Tensor:
+    """ttdft_ritz_residuals: || H psi_j - lambda_j psi_j ||_2 for every column (FP64)."""
+    hs = H.c_struct()
+    n = Psi.shape[1]
+    if Psi.dtype != torch.float64 or lam.dtype != torch.float64:
+        raise TypeError("Psi and lambda must be float64")
+    res = torch.empty(n, dtype=torch.float64, device=Psi.device)
+    if work is None:
+        work = _work(_lib.load().ttdft_ritz_residuals_workspace(C.byref(hs), n), Psi.device)
+    _lib.call("ttdft_ritz_residuals", C.byref(hs), _ptr(Psi), _ld(Psi), _ptr(lam), n, _ptr(res),
+              _ptr(work), work.numel(), _stream())
+    return res
+
+
+def with_degree_backoff(run_pass, deg: int, on_breakdown=None):
+    """run_pass(deg) -> result; while it raises a Cholesky breakdown
+    (TTDFT_ERR_NOT_POSDEF: the filtered block is rank-deficient in FP64), call
+    on_breakdown(deg) and retry with half the degree, down to 1.  Other errors,
+    and a breakdown at degree 1, propagate.  Returns (degree used, result)."""
+    while True:
+        try:
+            return deg, run_pass(deg)
+        except _lib.TtdftError as err:
+            if err.name != "TTDFT_ERR_NOT_POSDEF" or deg == 1:
+                raise
+            if on_breakdown is not None:
+                on_breakdown(deg)
+            deg = max(1, deg // 2)
+
+
+def chfsi_solve(Hf: BsrMatrix, H64: BsrMatrix, X0: torch.Tensor, m: int, tol: float,
+                n_conv: int = None, max_iter: int = 20, m_first: int = None, bounds=None,
+                lanczos_k: int = 30, seed: int = 0, timed: bool = False):
+    """Algorithm 1 repeated to convergence (Sec. 3.4): the filter with Hf (any
+    supported precision), FP64 Rayleigh-Ritz with H64, Ritz residual norms; the
+    next pass starts from the Ritz vectors Psi with the scaling point a0 and the
+    cut a moved to the smallest and largest Ritz values, until the residuals of
+    the lowest n_conv pairs are at most tol.  The first pass uses `bounds`
+    (a0, a, b) if given, else Lanczos estimates: b = the safeguarded upper
+    bound, a0 = theta_min, a = (theta_min + b) / 2; it may use a higher degree
+    m_first (the paper raises m for a random start).  A pass whose filtered
+    block is rank-deficient in FP64 (Rayleigh-Ritz reports a Cholesky
+    breakdown: the filter spread the block's components over more than the
+    FP64 range) is repeated with half the degree.
+    With timed=True every history entry also holds the filter, Rayleigh-Ritz
+    and residual times (ms, HIP events on the current stream).
+    Returns (lambda, Psi, residuals, history)."""
+    n = X0.shape[1]
+    n_conv = n if n_conv is None else n_conv
+    if not 1 <= n_conv <= n:
+        raise ValueError("n_conv must be in 1 .. n")
+    if bounds is None:
+        _, _, b, th_min = lanczos_bounds(H64, lanczos_k, seed)
+        a0, a = th_min, 0.5 * (th_min + b)
+    else:
+        a0, a, b = bounds
+    fdt = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}[Hf.dtype]
+    xdt = torch.float64 if fdt == torch.float64 else torch.float32
+    X = X0 if X0.dtype == xdt else cast(X0, xdt)
+    rr_work = torch.empty(rayleigh_ritz_workspace(H64, n, xdt), dtype=torch.uint8, device=X0.device)
+    res_work = _work(_lib.load().ttdft_ritz_residuals_workspace(C.byref(H64.c_struct()), n), X0.device)
+    history = []
+    lam = Psi = res = None
+    for it in range(max_iter):
+        deg = m_first if (it == 0 and m_first) else m
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if timed else None
+        def one_pass(deg):
+            if timed:
+                ev[0].record()
+            Y = cheb_filter(Hf, X, deg, a, b, a0)
+            if timed:
+                ev[1].record()
+            return rayleigh_ritz(H64, Y, work=rr_work)
+
+        def note(deg):
+            history.append({"pass": it + 1, "m": deg, "a0": a0, "a": a, "b": b,
+                            "max_residual": None, "rank_deficient": True})
+
+        deg, (lam, Psi) = with_degree_backoff(one_pass, deg, note)
+        if timed:
+            ev[2].record()
+        res = ritz_residuals(H64, Psi, lam, work=res_work)
+        if timed:
+            ev[3].record()
+        worst = float(res[:n_conv].max())
+        rec = {"pass": it + 1, "m": deg, "a0": a0, "a": a, "b": b, "max_residual": worst}
+        if timed:
+            rec.update(filter_ms=ev[0].elapsed_time(ev[1]), rr_ms=ev[1].elapsed_time(ev[2]),
+                       residual_ms=ev[2].elapsed_time(ev[3]))
+        history.append(rec)
+        if worst <= tol:
+            break
+        a0, a = updated_bounds(lam, b)
+        X = Psi if xdt == torch.float64 else cast(Psi, xdt)
+    return lam, Psi, res, history

@@ -84,7 +84,7 @@ __device__ inline int tri_count(const double *alpha, const double *beta, int k, 
 // largest eigenvalue theta of T_k by bisection; the last component s_k of its
 // normalised eigenvector by the three-term recurrence of the tridiagonal
 // (rescaled against overflow); out = {theta, theta + |beta_{k+1} s_k|,
-// theta + beta_{k+1}}
+// theta + beta_{k+1}, theta_min} with theta_min the smallest eigenvalue of T_k
 __global__ void lz_bound_kernel(const double *alpha, const double *beta, int k, double *out) {
   if (threadIdx.x != 0) return;
   double lo = alpha[0], hi = alpha[0];
@@ -100,6 +100,19 @@ __global__ void lz_bound_kernel(const double *alpha, const double *beta, int k, 
     else lo = mid;
   }
   const double theta = hi;   // upper end of its bracket
+  // smallest eigenvalue: the lowest x with at least one eigenvalue below it
+  double lo1 = alpha[0], hi1 = alpha[0];
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? fabs(beta[i]) : 0.0) + (i + 1 < k ? fabs(beta[i + 1]) : 0.0);
+    lo1 = fmin(lo1, alpha[i] - r);
+    hi1 = fmax(hi1, alpha[i] + r);
+  }
+  for (int it = 0; it < 200 && hi1 - lo1 > 1e-15 * fmax(fabs(lo1), fabs(hi1)); ++it) {
+    const double mid = 0.5 * (lo1 + hi1);
+    if (mid == lo1 || mid == hi1) break;
+    if (tri_count(alpha, beta, k, mid) >= 1) hi1 = mid;
+    else lo1 = mid;
+  }
   double sp = 0.0, sc = 1.0, n2 = 1.0;
   for (int i = 0; i + 1 < k; ++i) {
     if (beta[i + 1] == 0.0) { sc = 0.0; break; }    // T_k splits: residual 0
@@ -113,17 +126,18 @@ __global__ void lz_bound_kernel(const double *alpha, const double *beta, int k, 
   out[0] = theta;
   out[1] = theta + fabs(beta[k]) * last;
   out[2] = theta + fabs(beta[k]);
+  out[3] = lo1;   // lower end of its bracket
 }
 
 }  // namespace
 
 size_t lanczos_work_bytes(int64_t rows, int k) {
-  return (size_t)(3 * rows + 2 * (k + 2) + 4) * sizeof(double);   // out[3] fits in the 4
+  return (size_t)(3 * rows + 2 * (k + 2) + 4) * sizeof(double);
 }
 
-// work: 3 vectors + alpha[k+1] + beta[k+2] + out[3]
+// work: 3 vectors + alpha[k+1] + beta[k+2] + out[4]
 hipError_t run_lanczos_bound(const ttdft_bsr &H, const int64_t *perm, int k, uint64_t seed,
-                             void *work, hipStream_t s, double host_out[3]) {
+                             void *work, hipStream_t s, double host_out[4]) {
   const int64_t rows = H.n_block_rows * 64;
   double *v0 = (double *)work, *v1 = v0 + rows, *w = v1 + rows;
   double *alpha = w + rows, *beta = alpha + (k + 1), *out = beta + (k + 2);
@@ -147,7 +161,7 @@ hipError_t run_lanczos_bound(const ttdft_bsr &H, const int64_t *perm, int k, uin
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-  return hipMemcpy(host_out, out, 3 * sizeof(double), hipMemcpyDeviceToHost);
+  return hipMemcpy(host_out, out, 4 * sizeof(double), hipMemcpyDeviceToHost);
 }
 
 }  // namespace ttdft

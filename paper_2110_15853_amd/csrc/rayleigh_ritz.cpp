@@ -357,10 +357,54 @@ ttdft_status ttdft_lanczos_upper_bound(const ttdft_bsr *H, const int64_t *perm, 
   if (k < 1 || k > 1000) return failf(TTDFT_ERR_SHAPE, "k = %d outside 1 .. 1000", k);
   const size_t need = lanczos_work_bytes(H->n_block_rows * 64, k);
   if (!work || work_bytes < need) return failf(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", need);
-  hipError_t e = run_lanczos_bound(*H, perm, k, seed, work, (hipStream_t)stream, bound);
+  double out[4];
+  hipError_t e = run_lanczos_bound(*H, perm, k, seed, work, (hipStream_t)stream, out);
   if (e != hipSuccess) return hip_fail(e, "lanczos");
-  if (!std::isfinite(bound[0]) || !std::isfinite(bound[1]) || !std::isfinite(bound[2]))
+  if (!std::isfinite(out[0]) || !std::isfinite(out[1]) || !std::isfinite(out[2]))
     return failf(TTDFT_ERR_NONFINITE, "non-finite Lanczos estimate");
+  for (int i = 0; i < 3; ++i) bound[i] = out[i];
+  return api_ok();
+}
+
+ttdft_status ttdft_lanczos_bounds(const ttdft_bsr *H, const int64_t *perm, int32_t k,
+                                  uint64_t seed, double *bounds, void *work, size_t work_bytes,
+                                  void *stream) {
+  ttdft_status st = check_h64(H);
+  if (st != TTDFT_OK) return st;
+  if (!perm || !bounds) return failf(TTDFT_ERR_NULL, "perm or bounds is NULL");
+  if (k < 1 || k > 1000) return failf(TTDFT_ERR_SHAPE, "k = %d outside 1 .. 1000", k);
+  const size_t need = lanczos_work_bytes(H->n_block_rows * 64, k);
+  if (!work || work_bytes < need) return failf(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", need);
+  double out[4];
+  hipError_t e = run_lanczos_bound(*H, perm, k, seed, work, (hipStream_t)stream, out);
+  if (e != hipSuccess) return hip_fail(e, "lanczos");
+  for (int i = 0; i < 4; ++i)
+    if (!std::isfinite(out[i])) return failf(TTDFT_ERR_NONFINITE, "non-finite Lanczos estimate");
+  for (int i = 0; i < 4; ++i) bounds[i] = out[i];
+  return api_ok();
+}
+
+size_t ttdft_ritz_residuals_workspace(const ttdft_bsr *H, int64_t n_vec) {
+  if (!H || H->n_block_rows < 1 || n_vec < 1) return 0;
+  return residual_work_bytes(H->n_block_rows * 64, n_vec);
+}
+
+ttdft_status ttdft_ritz_residuals(const ttdft_bsr *H, const double *Psi, int64_t ldp,
+                                  const double *lambda, int64_t n_vec, double *res, void *work,
+                                  size_t work_bytes, void *stream) {
+  ttdft_status st = check_h64(H);
+  if (st != TTDFT_OK) return st;
+  if (!Psi || !lambda || !res) return failf(TTDFT_ERR_NULL, "Psi, lambda or res is NULL");
+  if (n_vec < 1 || ldp < n_vec) return failf(TTDFT_ERR_SHAPE, "bad shape");
+  const int64_t rows = H->n_block_rows * 64;
+  const size_t need = residual_work_bytes(rows, n_vec);
+  if (!work || work_bytes < need) return failf(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", need);
+  const size_t pb = block_bytes(rows, ldp, n_vec, 8), vb = (size_t)n_vec * 8;
+  if (overlap(work, need, Psi, pb) || overlap(work, need, lambda, vb) || overlap(work, need, res, vb) ||
+      overlap(res, vb, Psi, pb) || overlap(res, vb, lambda, vb))
+    return failf(TTDFT_ERR_ALIAS, "buffers overlap");
+  hipError_t e = run_ritz_residuals(*H, Psi, ldp, lambda, n_vec, res, work, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "residual launch");
   return api_ok();
 }
 

@@ -95,8 +95,13 @@ hipError_t launch_sddmm(const ttdft_bsr &H, const void *Abar, int64_t lda, const
 
 // ---- Lanczos estimate of the top of the spectrum
 // host_out: theta_max, theta_max + |beta_{k+1} s_k|, theta_max + beta_{k+1}
+// Ritz residual norms || H psi_j - lambda_j psi_j || (FP64 H)
+size_t residual_work_bytes(int64_t rows, int64_t n);
+hipError_t run_ritz_residuals(const ttdft_bsr &H, const double *Psi, int64_t ldp,
+                              const double *lambda, int64_t n, double *res, void *work,
+                              hipStream_t s);
 size_t lanczos_work_bytes(int64_t rows, int k);
 hipError_t run_lanczos_bound(const ttdft_bsr &H, const int64_t *perm, int k, uint64_t seed,
-                             void *work, hipStream_t s, double host_out[3]);
+                             void *work, hipStream_t s, double host_out[4]);
 
 }  // namespace ttdft

@@ -242,3 +242,32 @@ def test_lanczos_validation(lib_built):
     assert L.STATUS[lib.ttdft_lanczos_upper_bound(C.byref(H64), FAKE, 0, 0, out, FAKE, 1 << 30, None)] == "TTDFT_ERR_SHAPE"
     assert L.STATUS[lib.ttdft_lanczos_upper_bound(C.byref(H64), None, 10, 0, out, FAKE, 1 << 30, None)] == "TTDFT_ERR_NULL"
     assert L.STATUS[lib.ttdft_lanczos_upper_bound(C.byref(H64), FAKE, 10, 0, out, FAKE, 8, None)] == "TTDFT_ERR_WORKSPACE"
+
+
+def test_lanczos_bounds_and_residuals_validation(lib_built):
+    L = _lib()
+    lib = L.load()
+    H64, H32 = _fake_bsr(), _fake_bsr(dtype=1)
+    out = (C.c_double * 4)()
+    lb = lambda H=H64, perm=FAKE, k=10, o=out, wb=1 << 30: lib.ttdft_lanczos_bounds(C.byref(H), perm, k, 0, o, FAKE, wb, None)
+    assert L.STATUS[lb(H=H32)] == "TTDFT_ERR_DTYPE"
+    assert L.STATUS[lb(k=0)] == "TTDFT_ERR_SHAPE"
+    assert L.STATUS[lb(perm=None)] == "TTDFT_ERR_NULL"
+    assert L.STATUS[lb(o=None)] == "TTDFT_ERR_NULL"
+    assert L.STATUS[lb(wb=8)] == "TTDFT_ERR_WORKSPACE"
+    n = 32
+    need = lib.ttdft_ritz_residuals_workspace(C.byref(H64), n)
+    rows = H64.n_block_rows * 64
+    assert need >= rows * n * 8
+    W = FAKE + (1 << 36)            # fake addresses far apart: no overlap unless asked for
+    psi, lam, res = FAKE, FAKE + (1 << 34), FAKE + (1 << 35)
+    rr = lambda H=H64, p=psi, ld=n, l=lam, nv=n, r=res, w=W, wb=need: lib.ttdft_ritz_residuals(
+        C.byref(H), p, ld, l, nv, r, w, wb, None)
+    assert L.STATUS[rr(H=H32)] == "TTDFT_ERR_DTYPE"
+    assert L.STATUS[rr(p=None)] == "TTDFT_ERR_NULL"
+    assert L.STATUS[rr(r=None)] == "TTDFT_ERR_NULL"
+    assert L.STATUS[rr(ld=n - 1)] == "TTDFT_ERR_SHAPE"
+    assert L.STATUS[rr(nv=0)] == "TTDFT_ERR_SHAPE"
+    assert L.STATUS[rr(wb=need - 8)] == "TTDFT_ERR_WORKSPACE"
+    assert L.STATUS[rr(r=psi + 8)] == "TTDFT_ERR_ALIAS"
+    assert L.STATUS[rr(w=psi)] == "TTDFT_ERR_ALIAS"

@@ -339,3 +339,42 @@ def test_rayleigh_ritz_galerkin_condition():
     assert np.max(np.abs(Y.T @ Rres)) < 1e-10 * np.abs(Y).max()
     assert np.max(np.abs(Psi.T @ (H @ Psi) - np.diag(lam))) < 1e-12
     assert np.all(np.diff(lam) >= 0)
+
+
+def test_ritz_residuals_exact_eigenpairs():
+    # exact eigenpairs of a symmetric matrix have zero residual up to rounding
+    ip, ix, d, N = workload.lattice_hamiltonian(5, 2, 3)
+    H = oracle.csr_from_arrays(ip, ix, d, N)
+    lam, V = np.linalg.eigh(H.toarray())
+    res = oracle.ritz_residuals(H, V[:, :20], lam[:20])
+    assert res.max() <= 1e-12 * np.abs(lam).max()
+
+
+def test_ritz_residuals_closed_form():
+    # psi = cos(t) v1 + sin(t) v2 for orthonormal eigenvectors (mu1, mu2) and any
+    # value l: ||H psi - l psi||^2 = cos^2(t) (mu1 - l)^2 + sin^2(t) (mu2 - l)^2
+    rng = np.random.default_rng(7)
+    Q, _ = np.linalg.qr(rng.standard_normal((30, 30)))
+    mu = np.linspace(-3.0, 5.0, 30)
+    H = sp.csr_matrix((Q * mu) @ Q.T)
+    t = np.array([0.0, 0.3, 1.1, np.pi / 2])
+    i1, i2 = 4, 17
+    Psi = np.cos(t)[None, :] * Q[:, [i1]] + np.sin(t)[None, :] * Q[:, [i2]]
+    l = np.array([0.5, -1.0, mu[i1], 2.0])
+    want = np.sqrt(np.cos(t) ** 2 * (mu[i1] - l) ** 2 + np.sin(t) ** 2 * (mu[i2] - l) ** 2)
+    np.testing.assert_allclose(oracle.ritz_residuals(H, Psi, l), want, rtol=1e-12, atol=1e-13)
+
+
+def test_chfsi_passes_converge_to_lowest_eigenvalues():
+    # repeated passes of Algorithm 1 from a random block: the lowest Ritz values
+    # approach the lowest eigenvalues and their residuals shrink
+    ip, ix, d, N = workload.lattice_hamiltonian(6, 2, 1)
+    H = oracle.csr_from_arrays(ip, ix, d, N)
+    exact = np.linalg.eigvalsh(H.toarray())
+    X = workload.gaussian_block(N, 24, 1)
+    b = exact[-1] + 0.1
+    lam, Psi, res = oracle.chfsi(H, X, 10, float(exact[40]), b, float(exact[0]) - 1.0, passes=12)
+    keep = 16
+    assert np.abs(lam[:keep] - exact[:keep]).max() <= 1e-9
+    assert res[:keep].max() <= 1e-6
+    np.testing.assert_allclose(Psi.T @ Psi, np.eye(24), atol=1e-12)
