@@ -308,6 +308,49 @@ ttdft_status ttdft_ritz_residuals(const ttdft_bsr *H, const double *Psi, int64_t
                                   const double *lambda, int64_t n_vec, double *res, void *work,
                                   size_t work_bytes, void *stream);
 
+/* ---------------------------------------------------------------- occupancies and density */
+
+/* Bytes of device workspace ttdft_fermi_level needs (16). */
+size_t ttdft_fermi_level_workspace(void);
+
+/*
+ * Fermi-Dirac occupancies of the Ritz values (Sec. 2, occupancy and electron
+ * count equations): f_i = 1 / (1 + exp((lambda_i - mu) / kT)) with the Fermi
+ * energy mu solving 2 sum_i f_i = n_electrons (two electrons per orbital),
+ * found by bisection on the increasing count in one work-group (fixed-order
+ * sums).  lambda: device FP64 [n]; f: device FP64 [n]; mu: host double.
+ * Requires 0 < n_electrons < 2n and 0 < kT < inf (kT in the units of lambda,
+ * e.g. Hartree: k_B * 500 K = 1.5834e-3).  Synchronises the stream.
+ * Errors: NULL, SHAPE, BOUNDS, WORKSPACE, ALIAS, NONFINITE (a non-finite
+ * lambda), HIP.
+ */
+ttdft_status ttdft_fermi_level(const double *lambda, int64_t n, double n_electrons, double kT,
+                               double *f, double *mu, void *work, size_t work_bytes, void *stream);
+
+/*
+ * Density matrix of the occupied Ritz vectors on the pattern of H (the
+ * electron density of Sec. 2 in a localized basis needs it only where basis
+ * functions overlap, which is where H has entries):
+ *   P(i, j) of tile t = 2 sum_c f_c Psi[64B + i][c] Psi[64B' + j][c]
+ * for every stored tile t = (B, B'), written in the layout of the tile values
+ * (fragment order); entries whose mask bit is clear are written as 0 (mask
+ * NULL: every tile entry).  H must be FP64 (only its pattern is used).  Psi:
+ * device FP64 64*n_block_rows x n_vec (ldp); f: device FP64 [n_vec];
+ * P_vals: device FP64 [n_tiles*4096], overlapping none of the inputs.
+ * Deterministic.  ASYNC.  Errors: NULL, SHAPE, DTYPE, ALIAS, HIP.
+ */
+ttdft_status ttdft_density_matrix(const ttdft_bsr *H, const double *Psi, int64_t ldp, const double *f,
+                                  int64_t n_vec, double *P_vals, const uint64_t *mask, void *stream);
+
+/*
+ * Electron density at the lattice sites (the diagonal of the density matrix):
+ * rho[r] = 2 sum_c f_c Psi[r][c]^2 for r < rows.  Psi: device FP64 rows x n_vec
+ * (ldp); f: device FP64 [n_vec]; rho: device FP64 [rows], overlapping neither.
+ * Deterministic.  ASYNC.  Errors: NULL, SHAPE, ALIAS, HIP.
+ */
+ttdft_status ttdft_electron_density(const double *Psi, int64_t ldp, const double *f, int64_t rows,
+                                    int64_t n_vec, double *rho, void *stream);
+
 /* ---------------------------------------------------------------- adjoint of step 1 */
 
 /*

@@ -24,4 +24,7 @@ from .chfsi import (  # noqa: F401
     csr_from_arrays,
     ritz_residuals,
     chfsi,
+    fermi_occupancies,
+    density_matrix_on_pattern,
+    electron_density,
 )

@@ -199,3 +199,44 @@ def chfsi(H, X, m: int, a: float, b: float, a0: float, passes: int):
         a0, a = float(lam.min()), float(lam.max())
         X = Psi
     return lam, Psi, ritz_residuals(H, Psi, lam)
+
+
+def fermi_occupancies(eps, n_electrons: float, kT: float):
+    """Fermi-Dirac occupancies f_i = 1 / (1 + exp((eps_i - mu) / kT)) with the
+    Fermi energy mu fixed by the electron count 2 sum_i f_i = N_e (Sec. 2,
+    occupancy and electron-count equations).  mu by SciPy's bracketing root
+    finder on the increasing count, to full FP64 precision.  Returns (f, mu)."""
+    from scipy.optimize import brentq
+
+    eps = np.asarray(eps, dtype=np.float64)
+    if not 0.0 < n_electrons < 2.0 * eps.size:
+        raise ValueError("need 0 < N_e < 2n")
+
+    def occ(mu):
+        with np.errstate(over="ignore"):
+            return 1.0 / (1.0 + np.exp((eps - mu) / kT))
+
+    count = lambda mu: 2.0 * occ(mu).sum() - n_electrons
+    lo, hi = eps.min() - kT, eps.max() + kT
+    while count(lo) >= 0.0:
+        lo -= hi - lo
+    while count(hi) <= 0.0:
+        hi += hi - lo
+    mu = brentq(count, lo, hi, xtol=1e-16, rtol=8.9e-16, maxiter=500)
+    return occ(mu), mu
+
+
+def density_matrix_on_pattern(H, Psi, f):
+    """Density matrix P = Psi diag(2 f) Psi^T of the occupied Ritz vectors at the
+    stored entries of H (in H's CSR order): the electron density of Sec. 2 in a
+    localized basis needs it where basis functions overlap."""
+    H = sp.csr_matrix(H)
+    rows = np.repeat(np.arange(H.shape[0]), np.diff(H.indptr))
+    W = Psi * (2.0 * np.asarray(f))[None, :]
+    return np.einsum("ij,ij->i", W[rows], Psi[H.indices])
+
+
+def electron_density(Psi, f):
+    """rho_r = 2 sum_i f_i psi_ri^2 (Sec. 2, density equation, at the lattice
+    sites)."""
+    return 2.0 * (Psi * Psi) @ np.asarray(f)

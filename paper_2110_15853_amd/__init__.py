@@ -26,6 +26,10 @@ from .api import (  # noqa: F401
     lanczos_bounds,
     ritz_residuals,
     chfsi_solve,
+    fermi_level,
+    density_matrix,
+    electron_density,
+    KT_500K_HARTREE,
     gather_rows,
     project,
     rayleigh_ritz,

@@ -63,6 +63,10 @@ SIGNATURES = {
     "ttdft_lanczos_bounds": (_INT, [_BSRP, _P, _I32, C.c_uint64, _P, _P, _SZ, _P]),
     "ttdft_ritz_residuals_workspace": (_SZ, [_BSRP, _I64]),
     "ttdft_ritz_residuals": (_INT, [_BSRP, _P, _I64, _P, _I64, _P, _P, _SZ, _P]),
+    "ttdft_fermi_level_workspace": (_SZ, []),
+    "ttdft_fermi_level": (_INT, [_P, _I64, C.c_double, C.c_double, _P, _P, _P, _SZ, _P]),
+    "ttdft_density_matrix": (_INT, [_BSRP, _P, _I64, _P, _I64, _P, _P, _P]),
+    "ttdft_electron_density": (_INT, [_P, _I64, _P, _I64, _I64, _P, _P]),
     "ttdft_status_string": (C.c_char_p, [_INT]),
     "ttdft_last_error": (C.c_char_p, []),
     "ttdft_version": (C.c_char_p, []),

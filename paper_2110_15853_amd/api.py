@@ -427,3 +427,40 @@ def chfsi_solve(Hf: BsrMatrix, H64: BsrMatrix, X0: torch.Tensor, m: int, tol: fl
         a0, a = updated_bounds(lam, b)
         X = Psi if xdt == torch.float64 else cast(Psi, xdt)
     return lam, Psi, res, history
+
+
+KT_500K_HARTREE = 500.0 * 3.166811563e-6   # k_B T at the paper's smearing temperature, in Hartree
+
+
+def fermi_level(lam: torch.Tensor, n_electrons: float, kT: float = KT_500K_HARTREE):
+    """ttdft_fermi_level: Fermi-Dirac occupancies f and the Fermi energy mu with
+    2 sum f = n_electrons.  Returns (f, mu)."""
+    if lam.dtype != torch.float64:
+        raise TypeError("lambda must be float64")
+    f = torch.empty_like(lam)
+    mu = C.c_double()
+    w = _work(_lib.load().ttdft_fermi_level_workspace(), lam.device)
+    _lib.call("ttdft_fermi_level", _ptr(lam), lam.numel(), float(n_electrons), float(kT), _ptr(f),
+              C.byref(mu), _ptr(w), w.numel(), _stream())
+    return f, mu.value
+
+
+def density_matrix(H: BsrMatrix, Psi: torch.Tensor, f: torch.Tensor, use_mask: bool = True) -> torch.Tensor:
+    """ttdft_density_matrix: 2 sum_c f_c psi_ic psi_jc on the stored tiles of H,
+    [n_tiles, 4096] in the layout of the tile values (entry slot of a CSR entry:
+    H.entry_slot)."""
+    hs = H.c_struct()
+    n = Psi.shape[1]
+    P_vals = torch.empty((H.n_tiles, 4096), dtype=torch.float64, device=Psi.device)
+    _lib.call("ttdft_density_matrix", C.byref(hs), _ptr(Psi), _ld(Psi), _ptr(f), n, _ptr(P_vals),
+              _ptr(H.mask) if use_mask else C.c_void_p(0), _stream())
+    return P_vals
+
+
+def electron_density(Psi: torch.Tensor, f: torch.Tensor) -> torch.Tensor:
+    """ttdft_electron_density: rho_r = 2 sum_c f_c psi_rc^2 for every row of Psi
+    (blocked order for a blocked Psi)."""
+    rho = torch.empty(Psi.shape[0], dtype=torch.float64, device=Psi.device)
+    _lib.call("ttdft_electron_density", _ptr(Psi), _ld(Psi), _ptr(f), Psi.shape[0], Psi.shape[1],
+              _ptr(rho), _stream())
+    return rho

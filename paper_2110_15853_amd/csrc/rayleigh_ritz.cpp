@@ -408,4 +408,53 @@ ttdft_status ttdft_ritz_residuals(const ttdft_bsr *H, const double *Psi, int64_t
   return api_ok();
 }
 
+size_t ttdft_fermi_level_workspace(void) { return 2 * sizeof(double); }
+
+ttdft_status ttdft_fermi_level(const double *lambda, int64_t n, double n_electrons, double kT,
+                               double *f, double *mu, void *work, size_t work_bytes, void *stream) {
+  if (!lambda || !f || !mu) return failf(TTDFT_ERR_NULL, "lambda, f or mu is NULL");
+  if (n < 1) return failf(TTDFT_ERR_SHAPE, "n = %lld", (long long)n);
+  if (!(kT > 0.0) || !std::isfinite(kT)) return failf(TTDFT_ERR_BOUNDS, "kT must be positive and finite");
+  if (!(n_electrons > 0.0) || !(n_electrons < 2.0 * (double)n))
+    return failf(TTDFT_ERR_BOUNDS, "need 0 < n_electrons < 2n (n = %lld)", (long long)n);
+  if (!work || work_bytes < 2 * sizeof(double)) return failf(TTDFT_ERR_WORKSPACE, "workspace of 16 bytes needed");
+  const size_t vb = (size_t)n * 8;
+  if (overlap(lambda, vb, f, vb) || overlap(work, 16, f, vb) || overlap(work, 16, lambda, vb))
+    return failf(TTDFT_ERR_ALIAS, "buffers overlap");
+  int bad = 0;
+  hipError_t e = run_fermi_level(lambda, n, n_electrons, kT, f, (double *)work, (hipStream_t)stream, mu, &bad);
+  if (e != hipSuccess) return hip_fail(e, "fermi level");
+  if (bad) return failf(TTDFT_ERR_NONFINITE, "non-finite eigenvalue");
+  return api_ok();
+}
+
+ttdft_status ttdft_density_matrix(const ttdft_bsr *H, const double *Psi, int64_t ldp, const double *f,
+                                  int64_t n_vec, double *P_vals, const uint64_t *mask, void *stream) {
+  ttdft_status st = check_h64(H);
+  if (st != TTDFT_OK) return st;
+  if (!Psi || !f || !P_vals) return failf(TTDFT_ERR_NULL, "Psi, f or P_vals is NULL");
+  if (n_vec < 1 || ldp < n_vec) return failf(TTDFT_ERR_SHAPE, "bad shape");
+  const int64_t rows = H->n_block_rows * 64;
+  const size_t pb = block_bytes(rows, ldp, n_vec, 8), vb = (size_t)n_vec * 8;
+  const size_t hb = (size_t)H->n_tiles * kTileElems * 8;
+  if (overlap(P_vals, hb, Psi, pb) || overlap(P_vals, hb, f, vb) || overlap(P_vals, hb, H->vals, hb))
+    return failf(TTDFT_ERR_ALIAS, "buffers overlap");
+  hipError_t e = launch_sddmm(*H, Psi, ldp, Psi, ldp, n_vec, 2.0, P_vals, mask, false, TTDFT_F64,
+                              (hipStream_t)stream, f);
+  if (e != hipSuccess) return hip_fail(e, "density matrix launch");
+  return api_ok();
+}
+
+ttdft_status ttdft_electron_density(const double *Psi, int64_t ldp, const double *f, int64_t rows,
+                                    int64_t n_vec, double *rho, void *stream) {
+  if (!Psi || !f || !rho) return failf(TTDFT_ERR_NULL, "Psi, f or rho is NULL");
+  if (rows < 1 || n_vec < 1 || ldp < n_vec) return failf(TTDFT_ERR_SHAPE, "bad shape");
+  const size_t pb = block_bytes(rows, ldp, n_vec, 8);
+  if (overlap(rho, (size_t)rows * 8, Psi, pb) || overlap(rho, (size_t)rows * 8, f, (size_t)n_vec * 8))
+    return failf(TTDFT_ERR_ALIAS, "buffers overlap");
+  hipError_t e = launch_electron_density(Psi, ldp, f, rows, n_vec, rho, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "electron density launch");
+  return api_ok();
+}
+
 }  // extern "C"

@@ -3,7 +3,9 @@
 //     dH[t](i, j) (+)= coef * sum_c Abar[64*B + i][c] * Yk[64*B' + j][c]
 // for every stored tile t = (B, B'), entries outside the true pattern (mask bit
 // clear) written as 0.  dH has the layout of the tile values (fragment order:
-// entry (i, j) at 64*(4*(j/4) + i/16) + 16*(j%4) + i%16).  One work-group owns one tile and sweeps the vector
+// entry (i, j) at 64*(4*(j/4) + i/16) + 16*(j%4) + i%16).  An optional weight
+// per vector c multiplies Abar[.][c] (the density matrix on the pattern of H is
+// this product with weights 2 f_c and Abar = Yk = Psi).  One work-group owns one tile and sweeps the vector
 // dimension in 32-wide panels, both operands staged transposed in LDS
 // ([vector][row]) so every matrix-core operand read is 16 consecutive values.
 // FP64 inputs use the f64 16x16x4 op; FP32 and BF16 inputs accumulate in FP32
@@ -45,7 +47,7 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
     const int32_t *__restrict__ rowptr, const int32_t *__restrict__ tcol, int64_t n_block_rows,
     const TX *__restrict__ Abar, int64_t lda, const TX *__restrict__ Yk, int64_t ldb,
     int64_t n_vec, TC coef, TC *__restrict__ dH, const uint64_t *__restrict__ mask,
-    int accumulate) {
+    int accumulate, const double *__restrict__ colw) {
   using O = Op<TC>;
   __shared__ TC sA[BK][64 + 1];
   __shared__ TC sB[BK][64 + 1];
@@ -71,7 +73,8 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
       const int r = idx / BK, kk = idx % BK;     // consecutive threads walk the vector index
       const int64_t c = c0 + kk;
       const bool in = c < n_vec;
-      sA[kk][r] = in ? widen<TC, TX>(Ar[(int64_t)r * lda + c]) : TC(0);
+      const TC wa = (in && colw) ? (TC)colw[c] : TC(1);
+      sA[kk][r] = in ? wa * widen<TC, TX>(Ar[(int64_t)r * lda + c]) : TC(0);
       sB[kk][r] = in ? widen<TC, TX>(Br[(int64_t)r * ldb + c]) : TC(0);
     }
     __syncthreads();
@@ -107,22 +110,22 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
 
 hipError_t launch_sddmm(const ttdft_bsr &H, const void *Abar, int64_t lda, const void *Bk,
                         int64_t ldb, int64_t n_vec, double coef, void *dH, const uint64_t *mask,
-                        bool accumulate, ttdft_dtype xt, hipStream_t s) {
+                        bool accumulate, ttdft_dtype xt, hipStream_t s, const double *colw) {
   if (H.n_tiles == 0) return hipSuccess;
   const dim3 grid((unsigned)H.n_tiles), block(THREADS);
   const int acc = accumulate ? 1 : 0;
   if (xt == TTDFT_F64)
     hipLaunchKernelGGL((sddmm_kernel<double, double>), grid, block, 0, s, H.tile_rowptr, H.tile_col,
                        H.n_block_rows, (const double *)Abar, lda, (const double *)Bk, ldb, n_vec,
-                       coef, (double *)dH, mask, acc);
+                       coef, (double *)dH, mask, acc, colw);
   else if (xt == TTDFT_F32)
     hipLaunchKernelGGL((sddmm_kernel<float, float>), grid, block, 0, s, H.tile_rowptr, H.tile_col,
                        H.n_block_rows, (const float *)Abar, lda, (const float *)Bk, ldb, n_vec,
-                       (float)coef, (float *)dH, mask, acc);
+                       (float)coef, (float *)dH, mask, acc, colw);
   else
     hipLaunchKernelGGL((sddmm_kernel<__bf16, float>), grid, block, 0, s, H.tile_rowptr, H.tile_col,
                        H.n_block_rows, (const __bf16 *)Abar, lda, (const __bf16 *)Bk, ldb, n_vec,
-                       (float)coef, (float *)dH, mask, acc);
+                       (float)coef, (float *)dH, mask, acc, colw);
   return hipGetLastError();
 }
 

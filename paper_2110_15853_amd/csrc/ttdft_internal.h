@@ -91,7 +91,15 @@ hipError_t run_syev(int64_t n, const double *A, int64_t lda, double *lambda, dou
 // ---- adjoint helper: dH[t] (+)= coef * Abar[rowblock(t)] * B[colblock(t)]^T on the pattern
 hipError_t launch_sddmm(const ttdft_bsr &H, const void *Abar, int64_t lda, const void *Bk,
                         int64_t ldb, int64_t n_vec, double coef, void *dH, const uint64_t *mask,
-                        bool accumulate, ttdft_dtype xt, hipStream_t s);
+                        bool accumulate, ttdft_dtype xt, hipStream_t s,
+                        const double *colw = nullptr);
+
+// ---- occupancies and density (FP64)
+// mu with 2 sum_i f(lambda_i; mu) = n_electrons, f = Fermi-Dirac at kT; host_out = {mu, status}
+hipError_t run_fermi_level(const double *lambda, int64_t n, double n_electrons, double kT, double *f,
+                           double *scratch, hipStream_t s, double *mu, int *nonfinite);
+hipError_t launch_electron_density(const double *Psi, int64_t ldp, const double *f, int64_t rows,
+                                   int64_t n, double *rho, hipStream_t s);
 
 // ---- Lanczos estimate of the top of the spectrum
 // host_out: theta_max, theta_max + |beta_{k+1} s_k|, theta_max + beta_{k+1}

@@ -271,3 +271,36 @@ def test_lanczos_bounds_and_residuals_validation(lib_built):
     assert L.STATUS[rr(wb=need - 8)] == "TTDFT_ERR_WORKSPACE"
     assert L.STATUS[rr(r=psi + 8)] == "TTDFT_ERR_ALIAS"
     assert L.STATUS[rr(w=psi)] == "TTDFT_ERR_ALIAS"
+
+
+def test_density_entry_points_validation(lib_built):
+    L = _lib()
+    lib = L.load()
+    H64, H32 = _fake_bsr(), _fake_bsr(dtype=1)
+    mu = C.c_double()
+    lam, f, w = FAKE, FAKE + (1 << 30), FAKE + (1 << 31)
+    fl = lambda l=lam, n=16, ne=10.0, kT=0.01, ff=f, ww=w, wb=16: lib.ttdft_fermi_level(
+        l, n, ne, kT, ff, C.byref(mu), ww, wb, None)
+    assert lib.ttdft_fermi_level_workspace() == 16
+    assert L.STATUS[fl(l=None)] == "TTDFT_ERR_NULL"
+    assert L.STATUS[fl(n=0)] == "TTDFT_ERR_SHAPE"
+    assert L.STATUS[fl(kT=0.0)] == "TTDFT_ERR_BOUNDS"
+    assert L.STATUS[fl(kT=float("inf"))] == "TTDFT_ERR_BOUNDS"
+    assert L.STATUS[fl(ne=0.0)] == "TTDFT_ERR_BOUNDS"
+    assert L.STATUS[fl(ne=32.0)] == "TTDFT_ERR_BOUNDS"          # = 2n: no finite mu
+    assert L.STATUS[fl(wb=8)] == "TTDFT_ERR_WORKSPACE"
+    assert L.STATUS[fl(ff=lam + 8)] == "TTDFT_ERR_ALIAS"
+    psi, P_out = FAKE + (1 << 36), FAKE + (1 << 40)
+    dm = lambda H=H64, p=psi, ld=32, ff=f, n=32, out=P_out: lib.ttdft_density_matrix(
+        C.byref(H), p, ld, ff, n, out, None, None)
+    assert L.STATUS[dm(H=H32)] == "TTDFT_ERR_DTYPE"
+    assert L.STATUS[dm(p=None)] == "TTDFT_ERR_NULL"
+    assert L.STATUS[dm(out=None)] == "TTDFT_ERR_NULL"
+    assert L.STATUS[dm(ld=31)] == "TTDFT_ERR_SHAPE"
+    assert L.STATUS[dm(out=psi + 64)] == "TTDFT_ERR_ALIAS"
+    ed = lambda p=psi, ld=32, ff=f, rows=512, n=32, rho=P_out: lib.ttdft_electron_density(
+        p, ld, ff, rows, n, rho, None)
+    assert L.STATUS[ed(p=None)] == "TTDFT_ERR_NULL"
+    assert L.STATUS[ed(rows=0)] == "TTDFT_ERR_SHAPE"
+    assert L.STATUS[ed(ld=16)] == "TTDFT_ERR_SHAPE"
+    assert L.STATUS[ed(rho=psi + 8)] == "TTDFT_ERR_ALIAS"

@@ -378,3 +378,57 @@ def test_chfsi_passes_converge_to_lowest_eigenvalues():
     assert np.abs(lam[:keep] - exact[:keep]).max() <= 1e-9
     assert res[:keep].max() <= 1e-6
     np.testing.assert_allclose(Psi.T @ Psi, np.eye(24), atol=1e-12)
+
+
+def test_fermi_occupancies_degenerate_closed_form():
+    # n equal levels e0: every f = N_e / (2n) and mu = e0 - kT ln(2n/N_e - 1)
+    e0, n, ne, kT = -0.7, 40, 30.0, 0.01
+    f, mu = oracle.fermi_occupancies(np.full(n, e0), ne, kT)
+    np.testing.assert_allclose(f, ne / (2 * n), rtol=1e-13)
+    assert abs(mu - (e0 - kT * np.log(2 * n / ne - 1))) <= 1e-13
+
+
+def test_fermi_occupancies_symmetric_two_levels():
+    # levels -d and +d, half filled: mu = 0 by symmetry, f = 1 / (1 + exp(-+d / kT))
+    d, kT = 0.3, 0.05
+    eps = np.r_[np.full(10, -d), np.full(10, d)]
+    f, mu = oracle.fermi_occupancies(eps, 20.0, kT)
+    assert abs(mu) <= 1e-14
+    np.testing.assert_allclose(f[:10], 1 / (1 + np.exp(-d / kT)), rtol=1e-13)
+    np.testing.assert_allclose(f[10:], 1 / (1 + np.exp(d / kT)), rtol=1e-13)
+
+
+def test_fermi_occupancies_count_and_order():
+    rng = np.random.default_rng(3)
+    eps = np.sort(rng.uniform(-2, 1, 200))
+    for ne in (1.0, 57.3, 300.0, 399.0):
+        f, mu = oracle.fermi_occupancies(eps, ne, 1.5834e-3)
+        assert abs(2 * f.sum() - ne) <= 1e-10 * ne
+        assert np.all(np.diff(f) <= 0) and np.all((f >= 0) & (f <= 1))
+
+
+def test_density_invariants():
+    # for Ritz pairs: sum_r rho_r = 2 sum f (orthonormal Psi) and
+    # tr(P H) = sum over the pattern of P_rs H_rs = 2 sum_i f_i lambda_i
+    ip, ix, d, N = workload.lattice_hamiltonian(6, 2, 2)
+    H = oracle.csr_from_arrays(ip, ix, d, N)
+    lam, Psi = oracle.rayleigh_ritz(H, workload.gaussian_block(N, 30, 2))
+    f, mu = oracle.fermi_occupancies(lam, 24.0, 0.05)
+    rho = oracle.electron_density(Psi, f)
+    assert abs(rho.sum() - 24.0) <= 1e-10
+    Pv = oracle.density_matrix_on_pattern(H, Psi, f)
+    assert abs(np.dot(Pv, H.data) - 2 * np.dot(f, lam)) <= 1e-10 * np.abs(lam).max()
+    # the diagonal entries of P on the pattern are the density
+    diag = np.array([Pv[H.indptr[r]:H.indptr[r + 1]][H.indices[H.indptr[r]:H.indptr[r + 1]] == r][0]
+                     for r in range(N)])
+    np.testing.assert_allclose(diag, rho, rtol=1e-12, atol=1e-15)
+
+
+def test_density_matrix_complete_basis_is_twice_identity():
+    # all orbitals of a complete orthonormal basis fully occupied: P = 2 I
+    ip, ix, d, N = workload.lattice_hamiltonian(4, 1, 0)
+    H = oracle.csr_from_arrays(ip, ix, d, N)
+    _, V = np.linalg.eigh(H.toarray())
+    Pv = oracle.density_matrix_on_pattern(H, V, np.ones(N))
+    rows = np.repeat(np.arange(N), np.diff(H.indptr))
+    np.testing.assert_allclose(Pv, np.where(rows == H.indices, 2.0, 0.0), atol=1e-13)
