@@ -63,7 +63,8 @@ def cpu_baseline(Hc, X, cfg, n_cols):
 
 
 def mixed_precision_report(P, torch, ip, ix, d, cfg, H64, Xb64, keep_frac=1800 / 2048, reps=3):
-    """Low-precision filters (FP32; BF16 H with FP32 iterates) followed by the
+    """Low-precision filters (FP32; BF16 H with FP32 iterates; bf16x3 split
+    products with FP32 iterates) followed by the
     FP64 Rayleigh-Ritz with FP64 H, against the FP64 pipeline from the same
     start block: timing of the filters, and the error of the lowest Ritz values
     and the largest principal angle between the Ritz subspaces, from a random
@@ -94,7 +95,7 @@ def mixed_precision_report(P, torch, ip, ix, d, cfg, H64, Xb64, keep_frac=1800 /
     lam_c, psi_c = P.rayleigh_ritz(H64, filt(H64, Xb64))
     Xw = psi_c.clone()
     lam_w, psi_w = P.rayleigh_ritz(H64, filt(H64, Xw))
-    for name, hdt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+    for name, hdt in (("f32", torch.float32), ("bf16", torch.bfloat16), ("bf16x3", "bf16x3")):
         H = P.bsr_build(ip, ix, d, cfg.r, dtype=hdt, device="cuda")
         Xl = P.cast(Xb64, torch.float32)
         tl, _ = time_filter(H, Xl)

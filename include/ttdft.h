@@ -54,7 +54,14 @@ typedef enum {
   TTDFT_ERR_PATTERN = 12        /* CSR input malformed (unsorted, out of range)      */
 } ttdft_status;
 
-typedef enum { TTDFT_F64 = 0, TTDFT_F32 = 1, TTDFT_BF16 = 2 } ttdft_dtype;
+/*
+ * Element types.  TTDFT_BF16_SPLIT is a tile-value type only: each value h is
+ * held as a pair of bf16, hi = bf16(fp32(h)) and lo = bf16(fp32(h) - hi)
+ * (round to nearest even), so hi + lo carries 16 significant bits; the step
+ * kernel forms the three products hi*hi + hi*lo + lo*hi with the FP32
+ * iterates split the same way (bf16x3 on the bf16 matrix cores).
+ */
+typedef enum { TTDFT_F64 = 0, TTDFT_F32 = 1, TTDFT_BF16 = 2, TTDFT_BF16_SPLIT = 3 } ttdft_dtype;
 
 /*
  * Lattice-blocked BSR matrix (all arrays device, caller-owned).
@@ -76,7 +83,10 @@ typedef struct {
                                   matrix-core fragment order: entry (i, j) of tile t at
                                   t*4096 + 64*(4*(j/4) + i/16) + 16*(j%4) + i%16 (the 16x4
                                   sub-block of rows 16*(i/16).., columns 4*(j/4).. is 64
-                                  consecutive values, column-major inside)              */
+                                  consecutive values, column-major inside).  BF16_SPLIT:
+                                  [n_tiles*8192] bf16, tile t = the 4096 hi values at
+                                  t*8192 + p, then the 4096 lo values at t*8192 + 4096 + p
+                                  (p the fragment-order position above)                 */
   ttdft_dtype dtype;
   const uint64_t *frag_mask;   /* device [n_tiles] or NULL: bit (4*kk + mb) set when the 16x4
                                   sub-block rows 16mb..16mb+15, columns 4kk..4kk+3 of the tile
@@ -101,9 +111,10 @@ ttdft_status ttdft_bsr_plan(int32_t r, const int64_t *rowptr, const int32_t *col
  * with the sizes from ttdft_bsr_plan):
  *   tile_rowptr[n_block_rows+1], tile_col[n_tiles],
  *   vals[n_tiles*4096] of dtype (F64, F32 or BF16; rounding to nearest even), in
- *   the fragment order of ttdft_bsr.vals,
+ *   the fragment order of ttdft_bsr.vals ([n_tiles*8192] for BF16_SPLIT),
  *   perm[64*n_block_rows]: blocked row -> natural row, or -1 for a padding row,
- *   entry_slot[nnz] (may be NULL): flat index into vals of each CSR entry,
+ *   entry_slot[nnz] (may be NULL): flat index into vals of each CSR entry (of
+ *   its hi value for BF16_SPLIT; lo at +4096),
  *   mask[n_tiles*64] (may be NULL): bit j of word (t*64 + i) set when entry
  *   (i, j) of tile t is a stored CSR entry,
  *   frag_mask[n_tiles] (may be NULL): bit (4*kk + mb) set when the 16x4
@@ -165,6 +176,14 @@ ttdft_status ttdft_cheb_filter(const ttdft_bsr *H, const void *X, int64_t ldx, v
 ttdft_status ttdft_cast(const void *src, ttdft_dtype src_dtype, int64_t lds, void *dst,
                         ttdft_dtype dst_dtype, int64_t ldd, int64_t rows, int64_t cols,
                         void *stream);
+
+/*
+ * FP64 tile values (n_tiles*4096, fragment order, e.g. the vals of an F64
+ * ttdft_bsr) to the BF16_SPLIT layout (n_tiles*8192 bf16: per tile the hi
+ * values, then the lo values), on the device.  src, dst: device, not
+ * overlapping.  ASYNC.  Errors: NULL, SHAPE (n_tiles < 0), ALIAS, HIP.
+ */
+ttdft_status ttdft_split_bf16(const double *src, int64_t n_tiles, void *dst, void *stream);
 
 /*
  * Row gather: dst[i, :] = src[perm[i], :] for perm[i] >= 0 and 0 for

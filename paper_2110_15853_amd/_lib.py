@@ -9,7 +9,7 @@ import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
-F64, F32, BF16 = 0, 1, 2
+F64, F32, BF16, BF16_SPLIT = 0, 1, 2, 3
 STATUS = {0: "TTDFT_OK", 1: "TTDFT_ERR_NULL", 2: "TTDFT_ERR_SHAPE", 3: "TTDFT_ERR_DTYPE",
           4: "TTDFT_ERR_BOUNDS", 5: "TTDFT_ERR_DEGREE", 6: "TTDFT_ERR_ALIAS",
           7: "TTDFT_ERR_WORKSPACE", 8: "TTDFT_ERR_NOT_POSDEF", 9: "TTDFT_ERR_NO_CONVERGENCE",
@@ -63,6 +63,7 @@ SIGNATURES = {
     "ttdft_lanczos_bounds": (_INT, [_BSRP, _P, _I32, C.c_uint64, _P, _P, _SZ, _P]),
     "ttdft_ritz_residuals_workspace": (_SZ, [_BSRP, _I64]),
     "ttdft_ritz_residuals": (_INT, [_BSRP, _P, _I64, _P, _I64, _P, _P, _SZ, _P]),
+    "ttdft_split_bf16": (_INT, [_P, _I64, _P, _P]),
     "ttdft_fermi_level_workspace": (_SZ, []),
     "ttdft_fermi_level": (_INT, [_P, _I64, C.c_double, C.c_double, _P, _P, _P, _SZ, _P]),
     "ttdft_density_matrix": (_INT, [_BSRP, _P, _I64, _P, _I64, _P, _P, _P]),

@@ -12,10 +12,12 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import BF16, F32, F64, Bsr
+from ._lib import BF16, BF16_SPLIT, F32, F64, Bsr
 
-DTYPE_CODES = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
-_NP_STORAGE = {F64: np.float64, F32: np.float32, BF16: np.uint16}
+# "bf16x3": tile values as hi + lo bf16 pairs, products hi*hi + hi*lo + lo*hi
+DTYPE_CODES = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16, "bf16x3": BF16_SPLIT}
+_NP_STORAGE = {F64: np.float64, F32: np.float32, BF16: np.uint16, BF16_SPLIT: np.uint16}
+_TILE_VALUES = {F64: 4096, F32: 4096, BF16: 4096, BF16_SPLIT: 8192}   # stored values per tile
 
 
 def _code(t: torch.Tensor) -> int:
@@ -82,7 +84,7 @@ def bsr_build(indptr, indices, data, r: int, dtype=torch.float64, device="cuda")
     nbr, nt = nbr.value, nt.value
     tptr = np.empty(nbr + 1, np.int32)
     tcol = np.empty(nt, np.int32)
-    vals = np.empty(nt * 4096, _NP_STORAGE[code])
+    vals = np.empty(nt * _TILE_VALUES[code], _NP_STORAGE[code])
     perm = np.empty(nbr * 64, np.int64)
     slot = np.empty(len(data), np.int64)
     mask = np.empty(nt * 64, np.uint64)
@@ -94,12 +96,12 @@ def bsr_build(indptr, indices, data, r: int, dtype=torch.float64, device="cuda")
     inv = np.empty(N, np.int64)
     real = perm >= 0
     inv[perm[real]] = np.nonzero(real)[0]
-    tvals = torch.from_numpy(vals.view(np.int16)).view(torch.bfloat16) if code == BF16 \
+    tvals = torch.from_numpy(vals.view(np.int16)).view(torch.bfloat16) if code in (BF16, BF16_SPLIT) \
         else torch.from_numpy(vals)
     return BsrMatrix(r=r, N=N, n_block_rows=nbr, n_tiles=nt,
                      tile_rowptr=torch.from_numpy(tptr).to(device),
                      tile_col=torch.from_numpy(tcol).to(device),
-                     vals=tvals.reshape(nt, 4096).to(device),
+                     vals=tvals.reshape(nt, _TILE_VALUES[code]).to(device),
                      perm=torch.from_numpy(perm).to(device),
                      inv_perm=torch.from_numpy(inv).to(device),
                      entry_slot=slot,
@@ -282,11 +284,19 @@ def bsr_astype(H: BsrMatrix, dtype: torch.dtype) -> BsrMatrix:
     code = DTYPE_CODES[dtype]
     if code == H.dtype:
         return H
-    flat = H.vals.reshape(H.n_tiles * 64, 64)      # elementwise: the layout is the same for every dtype
-    vals = cast(flat, dtype).reshape(H.n_tiles, 4096)
+    slot = H.entry_slot
+    if code == BF16_SPLIT:
+        if H.dtype != F64:
+            raise ValueError("the bf16x3 split is made from FP64 tile values")
+        vals = torch.empty((H.n_tiles, 8192), dtype=torch.bfloat16, device=H.vals.device)
+        _lib.call("ttdft_split_bf16", _ptr(H.vals), H.n_tiles, _ptr(vals), _stream())
+        slot = (slot // 4096) * 8192 + slot % 4096          # position of the hi value
+    else:
+        flat = H.vals.reshape(H.n_tiles * 64, 64)  # elementwise: the layout is the same for every dtype
+        vals = cast(flat, dtype).reshape(H.n_tiles, 4096)
     return BsrMatrix(r=H.r, N=H.N, n_block_rows=H.n_block_rows, n_tiles=H.n_tiles,
                      tile_rowptr=H.tile_rowptr, tile_col=H.tile_col, vals=vals, perm=H.perm,
-                     inv_perm=H.inv_perm, entry_slot=H.entry_slot, mask=H.mask, dtype=code,
+                     inv_perm=H.inv_perm, entry_slot=slot, mask=H.mask, dtype=code,
                      frag_mask=H.frag_mask, skip_zero_fragments=H.skip_zero_fragments)
 
 
@@ -388,8 +398,7 @@ def chfsi_solve(Hf: BsrMatrix, H64: BsrMatrix, X0: torch.Tensor, m: int, tol: fl
         a0, a = th_min, 0.5 * (th_min + b)
     else:
         a0, a, b = bounds
-    fdt = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}[Hf.dtype]
-    xdt = torch.float64 if fdt == torch.float64 else torch.float32
+    xdt = torch.float64 if Hf.dtype == F64 else torch.float32
     X = X0 if X0.dtype == xdt else cast(X0, xdt)
     rr_work = torch.empty(rayleigh_ritz_workspace(H64, n, xdt), dtype=torch.uint8, device=X0.device)
     res_work = _work(_lib.load().ttdft_ritz_residuals_workspace(C.byref(H64.c_struct()), n), X0.device)

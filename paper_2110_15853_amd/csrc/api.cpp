@@ -36,6 +36,8 @@ ttdft_status hip_status(hipError_t e, const char *what) {
 }
 
 bool valid_dtype(int t) { return t == TTDFT_F64 || t == TTDFT_F32 || t == TTDFT_BF16; }
+// types of tile values (dense blocks cannot be BF16_SPLIT)
+bool valid_tile_dtype(int t) { return valid_dtype(t) || t == TTDFT_BF16_SPLIT; }
 
 // byte range [lo, hi) touched by a rows x cols block with leading dim ld
 struct Span {
@@ -61,7 +63,7 @@ bool overlap(const Span &a, const Span &b) {
 
 ttdft_status check_bsr(const ttdft_bsr *H) {
   if (!H) return fail(TTDFT_ERR_NULL, "H is NULL");
-  if (!valid_dtype(H->dtype)) return fail(TTDFT_ERR_DTYPE, "H dtype %d unknown", (int)H->dtype);
+  if (!valid_tile_dtype(H->dtype)) return fail(TTDFT_ERR_DTYPE, "H dtype %d unknown", (int)H->dtype);
   if (H->n_block_rows < 1 || H->n_tiles < 0)
     return fail(TTDFT_ERR_SHAPE, "H has %lld block rows and %lld tiles",
                 (long long)H->n_block_rows, (long long)H->n_tiles);
@@ -76,7 +78,15 @@ ttdft_status check_bsr(const ttdft_bsr *H) {
 // dtype pairs (H, X) the fused step supports
 bool supported_pair(ttdft_dtype h, ttdft_dtype x) {
   return (h == TTDFT_F64 && x == TTDFT_F64) || (h == TTDFT_F32 && x == TTDFT_F32) ||
-         (h == TTDFT_BF16 && (x == TTDFT_F32 || x == TTDFT_BF16));
+         (h == TTDFT_BF16 && (x == TTDFT_F32 || x == TTDFT_BF16)) ||
+         (h == TTDFT_BF16_SPLIT && x == TTDFT_F32);
+}
+
+float bf16_to_f32(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
 }
 
 uint16_t f32_to_bf16_rne(float f) {
@@ -226,7 +236,7 @@ ttdft_status ttdft_bsr_build(int32_t r, const int64_t *rowptr, const int32_t *co
                              uint64_t *mask, uint64_t *frag_mask) {
   if (!val || !tile_rowptr || !tile_col || !vals || !perm)
     return fail(TTDFT_ERR_NULL, "an output or val pointer is NULL");
-  if (!valid_dtype(dtype)) return fail(TTDFT_ERR_DTYPE, "dtype %d unknown", (int)dtype);
+  if (!valid_tile_dtype(dtype)) return fail(TTDFT_ERR_DTYPE, "dtype %d unknown", (int)dtype);
   ttdft_status st = check_csr(r, rowptr, col);
   if (st != TTDFT_OK) return st;
   Lattice L(r);
@@ -236,7 +246,7 @@ ttdft_status ttdft_bsr_build(int32_t r, const int64_t *rowptr, const int32_t *co
   const int64_t nt = (int64_t)tcol.size();
   std::copy(tptr.begin(), tptr.end(), tile_rowptr);
   std::copy(tcol.begin(), tcol.end(), tile_col);
-  std::memset(vals, 0, (size_t)nt * kTileElems * dtype_size(dtype));
+  std::memset(vals, 0, (size_t)nt * kTileElems * tile_value_bytes(dtype));
   if (mask) std::memset(mask, 0, (size_t)nt * 64 * sizeof(uint64_t));
   if (frag_mask) std::memset(frag_mask, 0, (size_t)nt * sizeof(uint64_t));
   for (int64_t p = 0; p < NB * 64; ++p) perm[p] = -1;
@@ -250,13 +260,20 @@ ttdft_status ttdft_bsr_build(int32_t r, const int64_t *rowptr, const int32_t *co
       const int32_t *first = tile_col + tptr[b], *last = tile_col + tptr[b + 1];
       const int64_t t = tptr[b] + (std::lower_bound(first, last, (int32_t)bc) - first);
       // fragment order: the 16x4 fragment (lc/4, l/16) is 64 consecutive values
-      const int64_t slot = t * kTileElems + 64 * (4 * (lc >> 2) + (l >> 4)) + 16 * (lc & 3) + (l & 15);
+      const int64_t pos = 64 * (4 * (lc >> 2) + (l >> 4)) + 16 * (lc & 3) + (l & 15);
+      const int64_t slot = (dtype == TTDFT_BF16_SPLIT ? 2 : 1) * t * kTileElems + pos;
       if (dtype == TTDFT_F64) {
         ((double *)vals)[slot] = val[p];
       } else if (dtype == TTDFT_F32) {
         ((float *)vals)[slot] = (float)val[p];
-      } else {
+      } else if (dtype == TTDFT_BF16) {
         ((uint16_t *)vals)[slot] = f32_to_bf16_rne((float)val[p]);
+      } else {
+        // hi + lo: the residual of fp32(h) - hi is exact in FP32
+        const float h32 = (float)val[p];
+        const uint16_t hi = f32_to_bf16_rne(h32);
+        ((uint16_t *)vals)[slot] = hi;
+        ((uint16_t *)vals)[slot + kTileElems] = f32_to_bf16_rne(h32 - bf16_to_f32(hi));
       }
       if (entry_slot) entry_slot[p] = slot;
       if (mask) mask[t * 64 + l] |= (uint64_t)1 << lc;
@@ -358,6 +375,14 @@ ttdft_status ttdft_cast(const void *src, ttdft_dtype src_dtype, int64_t lds, voi
     return fail(TTDFT_ERR_ALIAS, "cast buffers overlap");
   return hip_status(launch_cast(src, src_dtype, lds, dst, dst_dtype, ldd, rows, cols,
                                 (hipStream_t)stream), "cast launch");
+}
+
+ttdft_status ttdft_split_bf16(const double *src, int64_t n_tiles, void *dst, void *stream) {
+  if (!src || !dst) return fail(TTDFT_ERR_NULL, "src or dst is NULL");
+  if (n_tiles < 0) return fail(TTDFT_ERR_SHAPE, "n_tiles = %lld", (long long)n_tiles);
+  if (overlap(span_bytes(src, (size_t)n_tiles * kTileElems * 8), span_bytes(dst, (size_t)n_tiles * kTileElems * 4)))
+    return fail(TTDFT_ERR_ALIAS, "src and dst overlap");
+  return hip_status(launch_split_bf16(src, n_tiles, dst, (hipStream_t)stream), "split launch");
 }
 
 ttdft_status ttdft_gather_rows(const void *src, int64_t lds, int64_t rows_src, void *dst,

@@ -260,14 +260,21 @@ template <> __device__ inline __bf16 from_f32<__bf16>(float v) { return (__bf16)
 //    tile's contraction.
 //  - a 16x32 fragment is skipped when all eight 16x4 sub-blocks it covers are
 //    clear in the fragment mask.
-template <typename TX>
+//  - SPLIT (BF16_SPLIT tiles, FP32 iterates): the tile holds hi and lo bf16
+//    parts, each iterate value y is split into hi = bf16(y), lo = bf16(y - hi),
+//    and every fragment takes the three products hi*hi + hi*lo + lo*hi (the
+//    lo*lo term, 2^-16 relative, is dropped).
+template <typename TX, bool SPLIT>
 __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_bf16_pipe(
     const int32_t *__restrict__ rowptr, const int32_t *__restrict__ tcol,
     const __bf16 *__restrict__ vals, const TX *__restrict__ Yk, int64_t ldk,
     const TX *__restrict__ Yp, int64_t ldp, TX *Yo, int64_t ldo, int64_t n_vec, int64_t n_ct,
     int64_t n_block_rows, int64_t cgroup, int64_t n_wg, float alpha, float c, float beta,
     const uint64_t *__restrict__ frag_mask) {
-  __shared__ __attribute__((aligned(16))) __bf16 sH[2][2 * 4 * 64 * 8];   // [buf][kk][mb][lane][8]
+  constexpr int PARTS = SPLIT ? 2 : 1;
+  static_assert(!SPLIT || sizeof(TX) == 4, "split products need FP32 iterates");
+  // [buf][part][kk][mb][lane][8]
+  __shared__ __attribute__((aligned(16))) __bf16 sH[2][PARTS * 2 * 4 * 64 * 8];
   const int64_t L = group_order(blockIdx.x, n_wg, cgroup * ORDER_CHUNK);
   const int64_t per_group = n_block_rows * cgroup;
   const int64_t cg = L / per_group, rem = L % per_group;
@@ -286,10 +293,13 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_bf16_pipe(
   for (int j = 0; j < 4; ++j) acc[j] = v4f{0, 0, 0, 0};
   const int t_begin = rowptr[B], t_end = rowptr[B + 1];
 
-  // H staging: thread tid moves 8 consecutive bf16 of one tile row (16 bytes)
-  v8bf hreg;
+  // H staging: thread tid moves 8 consecutive stored bf16 (16 bytes) per part
+  v8bf hreg[PARTS];
   auto load_h = [&](int t) {
-    hreg = *reinterpret_cast<const v8bf *>(vals + (int64_t)t * kTileElems + 8 * tid);
+#pragma unroll
+    for (int pt = 0; pt < PARTS; ++pt)
+      hreg[pt] = *reinterpret_cast<const v8bf *>(vals + (int64_t)t * PARTS * kTileElems +
+                                                 pt * kTileElems + 8 * tid);
   };
   auto store_h = [&](int buf) {
     // thread tid holds stored values 8 tid .. 8 tid + 7: fragment f = tid / 8 of
@@ -297,9 +307,12 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_bf16_pipe(
     const int f = tid >> 3, fl0 = (tid & 7) * 8;
     const int i0 = 16 * (f & 3) + (fl0 & 15), j = 4 * (f >> 2) + (fl0 >> 4);
     const int kk = j >> 5, g = (j & 31) >> 3, e = j & 7, mb = i0 >> 4;
-    __bf16 *dst = &sH[buf][((kk * 4 + mb) * 64 + (i0 & 15) + 16 * g) * 8 + e];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) dst[8 * u] = hreg[u];
+    for (int pt = 0; pt < PARTS; ++pt) {
+      __bf16 *dst = &sH[buf][pt * kTileElems + ((kk * 4 + mb) * 64 + (i0 & 15) + 16 * g) * 8 + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) dst[8 * u] = hreg[pt][u];
+    }
   };
   // two register sets for the Y_k values: one being contracted, one being fetched
   TX bA[2][8], bB[2][8];
@@ -317,14 +330,24 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_bf16_pipe(
   auto mma_tile = [&](int buf, uint64_t fm, const TX (&src)[2][8]) {
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
-      v8bf b;
+      v8bf b, blo;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) b[q] = (__bf16)to_f32<TX>(src[kk][q]);
+      for (int q = 0; q < 8; ++q) {
+        const float y = to_f32<TX>(src[kk][q]);
+        b[q] = (__bf16)y;
+        if (SPLIT) blo[q] = (__bf16)(y - (float)b[q]);
+      }
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb) {
         if (((fm >> (32 * kk + mb)) & 0x11111111ull) == 0) continue;
         const v8bf a = *reinterpret_cast<const v8bf *>(&sH[buf][((kk * 4 + mb) * 64 + lane) * 8]);
         acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[mb], 0, 0, 0);
+        if (SPLIT) {
+          const v8bf alo = *reinterpret_cast<const v8bf *>(
+              &sH[buf][kTileElems + ((kk * 4 + mb) * 64 + lane) * 8]);
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, blo, acc[mb], 0, 0, 0);
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, b, acc[mb], 0, 0, 0);
+        }
       }
     }
   };
@@ -407,13 +430,18 @@ hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, con
     const int64_t n_groups = (ctp + cgroup - 1) / cgroup;
     const int64_t wg = n_groups * H.n_block_rows * cgroup;
     if (wg > 0x7fffffff) return hipErrorInvalidConfiguration;
-    if (xt == TTDFT_F32)
-      hipLaunchKernelGGL(cheb_step_bf16_pipe<float>, dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
+    if (H.dtype == TTDFT_BF16_SPLIT)
+      hipLaunchKernelGGL((cheb_step_bf16_pipe<float, true>), dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
+                         H.tile_rowptr, H.tile_col, (const __bf16 *)H.vals, (const float *)Yk, ldk,
+                         (const float *)Yp, ldp, (float *)Yo, ldo, n_vec, ctp, H.n_block_rows,
+                         cgroup, wg, (float)alpha, (float)c, (float)beta, H.frag_mask);
+    else if (xt == TTDFT_F32)
+      hipLaunchKernelGGL((cheb_step_bf16_pipe<float, false>), dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
                          H.tile_rowptr, H.tile_col, (const __bf16 *)H.vals, (const float *)Yk, ldk,
                          (const float *)Yp, ldp, (float *)Yo, ldo, n_vec, ctp, H.n_block_rows,
                          cgroup, wg, (float)alpha, (float)c, (float)beta, H.frag_mask);
     else
-      hipLaunchKernelGGL(cheb_step_bf16_pipe<__bf16>, dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
+      hipLaunchKernelGGL((cheb_step_bf16_pipe<__bf16, false>), dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
                          H.tile_rowptr, H.tile_col, (const __bf16 *)H.vals, (const __bf16 *)Yk,
                          ldk, (const __bf16 *)Yp, ldp, (__bf16 *)Yo, ldo, n_vec, ctp,
                          H.n_block_rows, cgroup, wg, (float)alpha, (float)c, (float)beta,

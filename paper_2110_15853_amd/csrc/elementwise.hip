@@ -10,9 +10,18 @@ namespace {
 template <typename S> __device__ inline double load_as_f64(const S *p) { return (double)*p; }
 template <> __device__ inline double load_as_f64<__bf16>(const __bf16 *p) { return (double)(float)*p; }
 
+// FP64 -> BF16 rounds through FP32 (nearest even at both steps).  The empty asm
+// makes the FP32 value exist: without it the compiler may fold the two
+// conversions into one rounding from FP64, which differs when the FP32 value is
+// a bf16 tie.
+__device__ inline __bf16 bf16_via_f32(double v) {
+  float f = (float)v;
+  asm volatile("" : "+v"(f));
+  return (__bf16)f;
+}
+
 template <typename D> __device__ inline void store_from_f64(D *p, double v) { *p = (D)v; }
-// FP64 -> BF16 rounds through FP32 (nearest even at both steps).
-template <> __device__ inline void store_from_f64<__bf16>(__bf16 *p, double v) { *p = (__bf16)(float)v; }
+template <> __device__ inline void store_from_f64<__bf16>(__bf16 *p, double v) { *p = bf16_via_f32(v); }
 
 template <typename S, typename D>
 __global__ __launch_bounds__(256) void cast_kernel(const S *__restrict__ src, int64_t lds,
@@ -81,6 +90,28 @@ hipError_t launch_gather_rows(const void *src, int64_t lds, void *dst, int64_t l
   else
     hipLaunchKernelGGL(gather_kernel<uint16_t>, dim3(g), dim3(256), 0, s, (const uint16_t *)src,
                        lds, (uint16_t *)dst, ldd, rows_dst, cols, perm);
+  return hipGetLastError();
+}
+
+namespace {
+// per tile: hi = bf16(fp32(h)), lo = bf16(fp32(h) - hi), the hi block then the lo block
+__global__ void split_bf16_kernel(const double *__restrict__ src, int64_t total, __bf16 *__restrict__ dst) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t t = e / kTileElems, p = e % kTileElems;
+    float h32 = (float)src[e];
+    asm volatile("" : "+v"(h32));   // two roundings, as bf16_via_f32
+    const __bf16 hi = (__bf16)h32;
+    dst[2 * t * kTileElems + p] = hi;
+    dst[2 * t * kTileElems + kTileElems + p] = (__bf16)(h32 - (float)hi);
+  }
+}
+}  // namespace
+
+hipError_t launch_split_bf16(const double *src, int64_t n_tiles, void *dst, hipStream_t s) {
+  const int64_t total = n_tiles * kTileElems;
+  if (total == 0) return hipSuccess;
+  const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 16384);
+  hipLaunchKernelGGL(split_bf16_kernel, dim3(g), dim3(256), 0, s, src, total, (__bf16 *)dst);
   return hipGetLastError();
 }
 

@@ -11,6 +11,8 @@ namespace ttdft {
 inline size_t dtype_size(ttdft_dtype t) {
   return t == TTDFT_F64 ? 8 : t == TTDFT_F32 ? 4 : 2;
 }
+// bytes of one tile value (BF16_SPLIT: a pair of bf16)
+inline size_t tile_value_bytes(ttdft_dtype t) { return t == TTDFT_BF16_SPLIT ? 4 : dtype_size(t); }
 
 constexpr int kTile = 64;                    // rows per lattice block (4x4x4)
 constexpr int64_t kTileElems = 64 * 64;
@@ -29,6 +31,7 @@ hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, con
 // ---- element-wise / layout kernels
 hipError_t launch_cast(const void *src, ttdft_dtype st, int64_t lds, void *dst, ttdft_dtype dt,
                        int64_t ldd, int64_t rows, int64_t cols, hipStream_t s);
+hipError_t launch_split_bf16(const double *src, int64_t n_tiles, void *dst, hipStream_t s);
 hipError_t launch_gather_rows(const void *src, int64_t lds, void *dst, int64_t ldd,
                               int64_t rows_dst, int64_t cols, const int64_t *perm, size_t elt,
                               hipStream_t s);

@@ -304,3 +304,43 @@ def test_density_entry_points_validation(lib_built):
     assert L.STATUS[ed(rows=0)] == "TTDFT_ERR_SHAPE"
     assert L.STATUS[ed(ld=16)] == "TTDFT_ERR_SHAPE"
     assert L.STATUS[ed(rho=psi + 8)] == "TTDFT_ERR_ALIAS"
+
+
+def test_bsr_builder_bf16_split(lib_built):
+    # hi = bf16(fp32(h)), lo = bf16(fp32(h) - hi), hi block then lo block per tile
+    import torch
+    (ip, ix, d, N), (nbr, nt, tptr, tcol, v64, perm, slot, mask, fmask) = _bsr_host(5, 2, 0)
+    L = _lib()
+    lib = L.load()
+    P = lambda a: C.c_void_p(a.ctypes.data)
+    vs = np.empty(nt * 8192, np.uint16)
+    slot3 = np.empty(len(d), np.int64)
+    tptr3, tcol3, perm3 = np.empty_like(tptr), np.empty_like(tcol), np.empty_like(perm)
+    assert lib.ttdft_bsr_build(5, P(ip), P(ix), P(d), 3, P(tptr3), P(tcol3), P(vs), P(perm3), P(slot3),
+                               None, None) == 0
+    assert np.array_equal(tptr3, tptr) and np.array_equal(tcol3, tcol) and np.array_equal(perm3, perm)
+    np.testing.assert_array_equal(slot3, (slot // 4096) * 8192 + slot % 4096)
+    bf = lambda u: torch.from_numpy(u.view(np.int16)).view(torch.bfloat16).float().numpy().astype(np.float64)
+    hi, lo = bf(vs[slot3]), bf(vs[slot3 + 4096])
+    h32 = d.astype(np.float32)
+    ref_hi = torch.from_numpy(h32).to(torch.bfloat16).float().numpy()
+    ref_lo = torch.from_numpy(h32 - ref_hi).to(torch.bfloat16).float().numpy()
+    np.testing.assert_array_equal(hi, ref_hi)
+    np.testing.assert_array_equal(lo, ref_lo)
+    assert np.abs(hi + lo - d).max() <= 2.0 ** -16 * np.abs(d).max()
+    # every other stored value is zero
+    rest = np.ones(vs.size, bool)
+    rest[slot3] = rest[slot3 + 4096] = False
+    assert not vs[rest].any()
+
+
+def test_split_and_step_validation(lib_built):
+    L = _lib()
+    lib = L.load()
+    assert L.STATUS[lib.ttdft_split_bf16(None, 4, FAKE, None)] == "TTDFT_ERR_NULL"
+    assert L.STATUS[lib.ttdft_split_bf16(FAKE, -1, FAKE * 1000, None)] == "TTDFT_ERR_SHAPE"
+    assert L.STATUS[lib.ttdft_split_bf16(FAKE, 4, FAKE + 64, None)] == "TTDFT_ERR_ALIAS"
+    # split tiles step only FP32 iterates
+    H = _fake_bsr(dtype=3)
+    assert L.STATUS[_filter(H=H, dt=2)] == "TTDFT_ERR_DTYPE"
+    assert L.STATUS[_filter(H=H, dt=0)] == "TTDFT_ERR_DTYPE"

@@ -13,12 +13,21 @@ from gpu_common import A, A0, B, normwise, require_gpu
 pytestmark = pytest.mark.gpu
 
 
+def _split_values(torch, d):
+    """hi + lo of the bf16x3 split, formed on the CPU from the documented rule
+    hi = bf16(fp32(h)), lo = bf16(fp32(h) - hi); exact in FP64."""
+    h32 = torch.from_numpy(d).float()
+    hi = h32.bfloat16().float()
+    lo = (h32 - hi).bfloat16().float()
+    return hi.double().numpy() + lo.double().numpy()
+
+
 def _setup(r, h, n, hdtype, seed=0):
     torch, P = require_gpu()
     ip, ix, d, N = workload.lattice_hamiltonian(r, h, seed)
     Hb = P.bsr_build(ip, ix, d, r, dtype=hdtype, device="cuda")
     # the oracle sees exactly the rounded values the GPU holds
-    dr = torch.from_numpy(d).to(hdtype).double().numpy()
+    dr = _split_values(torch, d) if hdtype == "bf16x3" else torch.from_numpy(d).to(hdtype).double().numpy()
     Hc = oracle.csr_from_arrays(ip, ix, dr, N)
     X = workload.gaussian_block(N, n, seed)
     return Hb, Hc, X
@@ -30,7 +39,11 @@ def _setup(r, h, n, hdtype, seed=0):
 # most about linearly in m: bound 4*m*u.  FP32: u = 2^-24 (m = 10: 2.4e-6,
 # m = 20: 4.8e-6).  BF16 operands: u = 2^-8, but a step's error is damped by
 # the later steps instead of accumulating, so one 2.5*u = 1e-2 suffices.
-U32, U16 = 2.0 ** -24, 2.0 ** -8
+# bf16x3 (hi + lo tiles, FP32 iterates split into hi + lo, three products per
+# fragment): the dropped lo*lo term and the truncation of the iterate split are
+# each below 2^-16 of a product, so each step is like FP32 with u = 2^-16:
+# bound 4*m*2^-16.
+U32, U16, U3 = 2.0 ** -24, 2.0 ** -8, 2.0 ** -16
 
 
 @pytest.mark.parametrize("hname,xname,r,n,m,tol", [
@@ -41,10 +54,12 @@ U32, U16 = 2.0 ** -24, 2.0 ** -8
     ("bf16", "bf16", 20, 64, 10, 2.5 * U16),
     ("bf16", "f32", 9, 130, 7, 2.5 * U16),         # ragged last column tile
     ("bf16", "bf16", 6, 37, 5, 2.5 * U16),         # padded lattice, ragged columns
+    ("bf16x3", "f32", 20, 64, 10, 4 * 10 * U3),
+    ("bf16x3", "f32", 9, 130, 7, 4 * 7 * U3),       # ragged last column tile
 ])
 def test_low_precision_filter_vs_oracle(hname, xname, r, n, m, tol):
     torch, P = require_gpu()
-    dt = {"f32": torch.float32, "bf16": torch.bfloat16}
+    dt = {"f32": torch.float32, "bf16": torch.bfloat16, "bf16x3": "bf16x3"}
     Hb, Hc, X = _setup(r, 3, n, dt[hname])
     Xb = P.cast(P.to_blocked(torch.from_numpy(X).cuda(), Hb), dt[xname])
     Xr = P.from_blocked(P.cast(Xb, torch.float64), Hb).cpu().numpy()   # rounded X, exact in FP64
@@ -67,6 +82,17 @@ def test_cast_round_trip_and_rounding():
     assert torch.equal(x16.cpu(), torch.from_numpy(X).float().bfloat16())  # FP64 -> FP32 -> BF16
     assert torch.equal(P.cast(x16, torch.float64).cpu(), x16.cpu().double())
     assert torch.equal(P.cast(x32, torch.bfloat16).cpu(), x32.cpu().bfloat16())
+    # FP64 values just off a bf16 tie that round to the tie in FP32: rounding
+    # twice (FP64 -> FP32 -> BF16, ties to even) differs from rounding once
+    base = torch.tensor([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(0.75 + 2.0 ** -9)], dtype=torch.float32)
+    ties = base.double().numpy()
+    off = np.concatenate([ties + 2.0 ** -40, ties - 2.0 ** -40]).reshape(2, 3)
+    want = torch.from_numpy(off).float().bfloat16()
+    m, e = np.frexp(off)                                  # one rounding to 8 significant bits
+    once = np.ldexp(np.round(m * 256.0) / 256.0, e)
+    assert (want.double().numpy() != once).sum() == 3     # the two rules differ here
+    got = P.cast(torch.from_numpy(off).cuda(), torch.bfloat16).cpu()
+    assert torch.equal(got.view(torch.int16), want.view(torch.int16))
 
 
 def _ritz(Hc, H64, Hlow, X0, m, xdt):
@@ -83,7 +109,28 @@ def _max_angle(U, V):
     return float(np.arccos(np.clip(s.min(), -1, 1)))
 
 
-@pytest.mark.parametrize("hname", ["f32", "bf16"])
+def test_bf16x3_device_split_matches_builder_and_beats_bf16():
+    torch, P = require_gpu()
+    ip, ix, d, N = workload.lattice_hamiltonian(12, 3, 0)
+    H64 = P.bsr_build(ip, ix, d, 12, dtype=torch.float64, device="cuda")
+    Hs = P.bsr_build(ip, ix, d, 12, dtype="bf16x3", device="cuda")
+    Hd = P.bsr_astype(H64, "bf16x3")
+    assert torch.equal(Hd.vals.view(torch.int16), Hs.vals.view(torch.int16))
+    np.testing.assert_array_equal(Hd.entry_slot, Hs.entry_slot)
+    # same filter, three tile formats: the split error is far below plain bf16's
+    Hc = oracle.csr_from_arrays(ip, ix, _split_values(torch, d), N)
+    X = workload.gaussian_block(N, 48, 1)
+    Xb = P.cast(P.to_blocked(torch.from_numpy(X).cuda(), H64), torch.float32)
+    Xr = P.from_blocked(P.cast(Xb, torch.float64), H64).cpu().numpy()
+    ref = oracle.cheb_filter(Hc, Xr, 10, A, B, A0)
+    e3 = normwise(P.from_blocked(P.cast(P.cheb_filter(Hd, Xb, 10, A, B, A0), torch.float64), H64).cpu().numpy(), ref)
+    Hb16 = P.bsr_astype(H64, torch.bfloat16)
+    e16 = normwise(P.from_blocked(P.cast(P.cheb_filter(Hb16, Xb, 10, A, B, A0), torch.float64), H64).cpu().numpy(), ref)
+    print(f"bf16x3 error {e3:.3e}, bf16 error {e16:.3e}", flush=True)
+    assert e3 <= 4 * 10 * U3 and e3 < e16 / 10
+
+
+@pytest.mark.parametrize("hname", ["f32", "bf16", "bf16x3"])
 def test_mixed_precision_ritz_values(hname):
     """Lowest 88% of the Ritz values of the mixed pipeline against the FP64
     pipeline, from a random start (cold) and from the FP64 Ritz vectors of one
@@ -91,7 +138,7 @@ def test_mixed_precision_ritz_values(hname):
     1e-6 Ha warm; BF16 is stated, not claimed."""
     torch, P = require_gpu()
     r, h, n, m = 20, 3, 64, 10
-    dt = {"f32": torch.float32, "bf16": torch.bfloat16}[hname]
+    dt = {"f32": torch.float32, "bf16": torch.bfloat16, "bf16x3": "bf16x3"}[hname]
     ip, ix, d, N = workload.lattice_hamiltonian(r, h, 0)
     Hc = oracle.csr_from_arrays(ip, ix, d, N)
     H64 = P.bsr_build(ip, ix, d, r, dtype=torch.float64, device="cuda")
