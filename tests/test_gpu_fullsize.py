@@ -67,3 +67,70 @@ def test_fullsize_rayleigh_ritz_properties(fullsize):
         # the filtered block has condition ~1e7 after column scaling, so its span is
         # known to ~1e7 * eps; the cosine is bounded by that over the residual size
         assert np.max(np.abs(gal)) <= 1e-6
+
+
+def _seeded(seed, n, lo, hi):
+    return np.random.default_rng(seed).uniform(lo, hi, n)
+
+
+def test_fullsize_ritz_residuals_sampled_columns(fullsize):
+    # the residual definition holds for any block: a seeded random block and
+    # seeded values stand in for Ritz pairs (inputs independent of the GPU path)
+    torch, P = require_gpu()
+    cfg, Hc, Hb, X, Yb = fullsize
+    Xb = P.to_blocked(torch.from_numpy(X).cuda(), Hb)
+    lam = _seeded(11, cfg.n, -15.0, 10.0)
+    res = P.ritz_residuals(Hb, Xb, torch.from_numpy(lam).cuda()).cpu().numpy()
+    cols = np.array([0, 5, 1023, 2000, 2047])
+    ref = oracle.ritz_residuals(Hc, np.ascontiguousarray(X[:, cols]), lam[cols])
+    np.testing.assert_allclose(res[cols], ref, rtol=1e-12)
+
+
+def test_fullsize_occupancies_and_density_sampled(fullsize):
+    torch, P = require_gpu()
+    cfg, Hc, Hb, X, Yb = fullsize
+    lam = np.sort(_seeded(12, cfg.n, -15.0, 10.0))
+    ne = 1.5 * cfg.n
+    f, mu = P.fermi_level(torch.from_numpy(lam).cuda(), ne, P.KT_500K_HARTREE)
+    f_ref, mu_ref = oracle.fermi_occupancies(lam, ne, P.KT_500K_HARTREE)
+    assert abs(mu - mu_ref) <= 1e-12 * max(1.0, abs(mu_ref))
+    assert np.abs(f.cpu().numpy() - f_ref).max() <= 1e-12
+    # density matrix and site density of the seeded block with these occupancies
+    Xb = P.to_blocked(torch.from_numpy(X).cuda(), Hb)
+    fd = torch.from_numpy(f_ref).cuda()
+    Pv = P.density_matrix(Hb, Xb, fd).reshape(-1).cpu().numpy()
+    rng = np.random.default_rng(13)
+    entries = rng.choice(len(Hc.data), 3000, replace=False)
+    rows = np.searchsorted(Hc.indptr, entries, side="right") - 1
+    cols = Hc.indices[entries]
+    want = 2.0 * np.einsum("ij,ij->i", X[rows] * f_ref[None, :], X[cols])
+    got = Pv[Hb.entry_slot[entries]]
+    np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-12 * np.abs(want).max())
+    rho = P.from_blocked(P.electron_density(Xb, fd).reshape(-1, 1), Hb).reshape(-1).cpu().numpy()
+    sites = rng.choice(X.shape[0], 500, replace=False)
+    np.testing.assert_allclose(rho[sites], oracle.electron_density(X[sites], f_ref), rtol=1e-12)
+
+
+@pytest.mark.parametrize("fmt", ["f32", "bf16x3"])
+def test_fullsize_reduced_precision_filter_sampled_columns(fullsize, fmt):
+    # the oracle filters the sampled columns with exactly the values the GPU holds:
+    # fp32(h), or hi + lo of the bf16x3 split formed on the CPU
+    torch, P = require_gpu()
+    cfg, Hc, Hb, X, Yb = fullsize
+    ip, ix, d, N = workload.lattice_hamiltonian(cfg.r, cfg.h, cfg.seed)
+    h32 = torch.from_numpy(d).float()
+    if fmt == "f32":
+        Hl, dr, u = P.bsr_astype(Hb, torch.float32), h32.double().numpy(), 2.0 ** -24
+    else:
+        hi = h32.bfloat16().float()
+        lo = (h32 - hi).bfloat16().float()
+        Hl, dr, u = P.bsr_astype(Hb, "bf16x3"), hi.double().numpy() + lo.double().numpy(), 2.0 ** -16
+    Xl = P.cast(P.to_blocked(torch.from_numpy(X).cuda(), Hb), torch.float32)
+    Yl = P.cheb_filter(Hl, Xl, cfg.m, cfg.a, cfg.b, cfg.a0)
+    cols = np.array([3, 1500, 2047])
+    Y = P.from_blocked(P.cast(Yl, torch.float64), Hb)[:, torch.from_numpy(cols).cuda()].cpu().numpy()
+    Xr = np.ascontiguousarray(X[:, cols].astype(np.float32).astype(np.float64))
+    ref = oracle.cheb_filter(oracle.csr_from_arrays(ip, ix, dr, N), Xr, cfg.m, cfg.a, cfg.b, cfg.a0)
+    err = normwise(Y, ref)
+    print(f"full-size {fmt} filter: normwise error {err:.3e}", flush=True)
+    assert err <= 4 * cfg.m * u
