@@ -367,7 +367,7 @@ SyevLayout syev_layout(int64_t n) {
   SyevLayout L;
   L.n = n;
   L.np = (n + 63) / 64 * 64;
-  L.splits = gemm_tn_splits(n, n);
+  L.splits = gemm_tn_splits(n, n, true);
   size_t off = 0;
   auto take = [&](size_t doubles) { size_t o = off; off += (doubles * 8 + 255) / 256 * 256; return o; };
   const size_t nn = (size_t)n * n, npnp = (size_t)L.np * L.np;

@@ -296,12 +296,22 @@ hipError_t launch_gemm_tn_acc(const double *A, int64_t lda, const double *B, int
   return hipGetLastError();
 }
 
-int gemm_tn_splits(int64_t rows, int64_t n) {
-  const int64_t tiles = ((n + BM - 1) / BM) * ((n + BM - 1) / BM);
-  int64_t s = (2048 + tiles - 1) / tiles;              // aim for >= 2048 work-groups
-  const int64_t max_by_k = (rows + 16 * BK - 1) / (16 * BK);  // at least 16 panels each
-  s = std::max<int64_t>(1, std::min<int64_t>(s, std::min<int64_t>(max_by_k, 64)));
-  return (int)s;
+// Split-K count of the TN product.  Every work-group of one launch does the same
+// work, so a last round of resident work-groups that is only partly filled
+// leaves the rest of the chip idle: take the smallest split count that gives at
+// least 3.5 rounds with the last one at least 95% full (two resident
+// work-groups on each of the 256 CUs), else about four rounds.
+int gemm_tn_splits(int64_t rows, int64_t n, bool sym) {
+  const int64_t tn = (n + BM - 1) / BM;
+  const int64_t tiles = sym ? tn * (tn + 1) / 2 : tn * tn;
+  const int64_t max_s =
+      std::max<int64_t>(1, std::min<int64_t>(64, (rows + 16 * BK - 1) / (16 * BK)));  // >= 16 panels each
+  constexpr int64_t kResident = 2 * 256;
+  for (int64_t s = 1; s <= max_s; ++s) {
+    const int64_t wg = tiles * s, rounds = (wg + kResident - 1) / kResident;
+    if (2 * wg >= 7 * kResident && 100 * wg >= 95 * rounds * kResident) return (int)s;
+  }
+  return (int)std::min<int64_t>(max_s, (4 * kResident + tiles - 1) / tiles);
 }
 
 hipError_t launch_gemm_tn(const double *A, int64_t lda, const double *B, int64_t ldb,

@@ -56,7 +56,7 @@ struct QrLayout {
 QrLayout qr_layout(int64_t rows, int64_t n) {
   QrLayout L;
   L.np = (n + 63) / 64 * 64;
-  L.splits = gemm_tn_splits(rows, n);
+  L.splits = gemm_tn_splits(rows, n, true);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
   L.w = take((size_t)rows * n * 8);
@@ -144,7 +144,7 @@ struct ProjLayout {
 };
 ProjLayout proj_layout(int64_t rows, int64_t n) {
   ProjLayout L;
-  L.splits = gemm_tn_splits(rows, n);
+  L.splits = gemm_tn_splits(rows, n, false);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
   L.hq = take((size_t)rows * n * 8);

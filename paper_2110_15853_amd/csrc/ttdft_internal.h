@@ -47,7 +47,7 @@ hipError_t launch_gemm_tn(const double *A, int64_t lda, const double *B, int64_t
 hipError_t launch_gemm_tn_ex(const double *A, int64_t lda, const double *B, int64_t ldb,
                              int64_t rows, int64_t n, double *C, int64_t ldc, bool sym,
                              bool symmetrize, double *partial, int splits, hipStream_t s);
-int gemm_tn_splits(int64_t rows, int64_t n);
+int gemm_tn_splits(int64_t rows, int64_t n, bool sym);
 // C[rows x n] (ldc) = A[rows x n] (lda) * B[n x n] (ldb); when upper is set B is upper
 // triangular and its zero blocks are skipped.
 hipError_t launch_gemm_nn(const double *A, int64_t lda, const double *B, int64_t ldb,
