@@ -134,6 +134,78 @@ __global__ __launch_bounds__(256) void rank2_fused_kernel(double *A, int64_t n, 
   }
 }
 
+// Step k's rank-2 update fused with step k+1's reflector and product, so that
+// the trailing block is read and written once per step.  Row k+1 (row 0 of the
+// step-k trailing block, the source of reflector k+1) is only read: every
+// work-group forms its updated entries itself and stages reflector k+1 in LDS
+// (m - 1 doubles of dynamic shared memory).  The rows and columns k+2 .. of A
+// (the trailing block of step k+1) are updated in place, one wave per row, and
+// each wave then forms its entry of p = tau A22 v for step k+1; column k+1,
+// which no later step reads, is left as it is.  p and pv of step k are read
+// and those of step k+1 written to separate buffers.  The arithmetic and the
+// summation order are those of house_symv_kernel and rank2_fused_kernel.
+__global__ __launch_bounds__(256) void tridiag_step_kernel(double *A, int64_t n, int64_t k,
+                                                           double *V, double *tau, double *d,
+                                                           double *e, const double *p,
+                                                           const double *pv, double *p1,
+                                                           double *pv1, int *nonfinite) {
+  extern __shared__ double vn[];
+  __shared__ double red[4], part[4];
+  const int64_t m = n - k - 1, m1 = m - 1, nparts = (m + 3) / 4;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < nparts; i += 256) s += pv[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  const double K = 0.5 * tau[k] * (red[0] + red[1] + red[2] + red[3]);
+  __syncthreads();                                     // red is reused below
+  const double *v = V + k * n + k + 1;                 // reflector k, v[0] = 1
+  const double *x = A + (k + 1) * n + k + 1;           // row k+1 before the update
+  const double w0 = p[0] - K * v[0];
+  for (int64_t j = 1 + threadIdx.x; j < m; j += 256) {
+    const double wj = p[j] - K * v[j];
+    vn[j - 1] = x[j] - (v[0] * wj + w0 * v[j]);
+  }
+  __syncthreads();
+  double t, scale, beta;
+  reflector(vn, m1, red, t, scale, beta);
+  __syncthreads();                                     // every thread has read vn[0]
+  for (int64_t i = threadIdx.x; i < m1; i += 256) vn[i] = i == 0 ? 1.0 : vn[i] * scale;
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    double *vo = V + (k + 1) * n + k + 2;
+    for (int64_t i = threadIdx.x; i < m1; i += 256) vo[i] = vn[i];
+    if (threadIdx.x == 0) {
+      if (!isfinite(beta) || !isfinite(t)) atomicExch(nonfinite, 1);
+      tau[k + 1] = t;
+      d[k + 1] = x[0] - (v[0] * w0 + w0 * v[0]);
+      e[k + 1] = beta;
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t r = (int64_t)blockIdx.x * 4 + wv;      // row of the step-(k+1) block
+  double pvr = 0.0;
+  if (r < m1) {
+    const int64_t i = r + 1;                           // its row in the step-k block
+    const double vi = v[i], wi = p[i] - K * vi;
+    double *row = A + (k + 1 + i) * n + k + 1;
+    double acc = 0.0;
+    for (int64_t j = 1 + lane; j < m; j += 64) {
+      const double wj = p[j] - K * v[j];
+      const double a = row[j] - (vi * wj + wi * v[j]);
+      row[j] = a;
+      acc += a * vn[j - 1];
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    const double pi = t * acc;
+    pvr = pi * vn[r];
+    if (lane == 0) p1[r] = pi;
+  }
+  if (lane == 0) part[wv] = pvr;
+  __syncthreads();
+  if (threadIdx.x == 0) pv1[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
 __global__ void tail_kernel(const double *A, int64_t n, double *d, double *e) {
   if (threadIdx.x != 0) return;
   if (n >= 2) {
@@ -298,6 +370,8 @@ __global__ __launch_bounds__(64) void inverse_iteration_kernel(
 // H_k0 H_k0+1 ... H_k1-1 = I - V T V^T, V = [v_k0 .. v_k1-1], T upper triangular
 // with T_jj = tau_j and T[0:j, j] = -tau_j T[0:j, 0:j] (V[:, 0:j]^T v_j).
 constexpr int WY_NB = 64;
+// largest n for the fused tridiagonalisation step (reflector staged in 64 KiB of LDS)
+constexpr int64_t kFusedTridiagMax = 8192;
 
 // Vb[i][j] = (v_{k0+j})_i, an n x nb row-major block: zero at and above row
 // k0+j, 1 at row k0+j+1
@@ -412,12 +486,31 @@ hipError_t run_syev(int64_t n, const double *Ain, int64_t lda, double *lambda, d
   hipLaunchKernelGGL(copy_matrix_kernel, dim3(grid_for(n * n)), dim3(256), 0, s, Ain, lda, A, n, n);
   // 1. tridiagonalisation; reflector vectors go to V (rows k, columns k+1..)
   double *V = du2;
-  for (int64_t k = 0; k + 2 < n; ++k) {
-    const int64_t m = n - k - 1;
-    hipLaunchKernelGGL(house_symv_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, A, n, k,
-                       V, tau, d, e, p, pv, info + 1);
-    hipLaunchKernelGGL(rank2_fused_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, A, n, k,
-                       V, tau, p, pv);
+  if (n <= kFusedTridiagMax) {
+    // one launch per step: step 0's product, then k's update fused with k+1's
+    // product (p, pv alternate between two buffers), then the last update
+    double *pb[2] = {p, vec + 5 * n}, *pvb[2] = {pv, vec + 6 * n};
+    if (n > 2)
+      hipLaunchKernelGGL(house_symv_kernel, dim3((unsigned)((n + 2) / 4)), dim3(256), 0, s, A, n,
+                         (int64_t)0, V, tau, d, e, pb[0], pvb[0], info + 1);
+    int cur = 0;
+    for (int64_t k = 0; k + 3 < n; ++k, cur ^= 1) {
+      const int64_t m1 = n - k - 2;
+      hipLaunchKernelGGL(tridiag_step_kernel, dim3((unsigned)((m1 + 3) / 4)), dim3(256),
+                         (unsigned)(m1 * sizeof(double)), s, A, n, k, V, tau, d, e, pb[cur],
+                         pvb[cur], pb[cur ^ 1], pvb[cur ^ 1], info + 1);
+    }
+    if (n > 2)
+      hipLaunchKernelGGL(rank2_fused_kernel, dim3((unsigned)((2 + 3) / 4)), dim3(256), 0, s, A, n,
+                         n - 3, V, tau, pb[cur], pvb[cur]);
+  } else {
+    for (int64_t k = 0; k + 2 < n; ++k) {
+      const int64_t m = n - k - 1;
+      hipLaunchKernelGGL(house_symv_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, A, n,
+                         k, V, tau, d, e, p, pv, info + 1);
+      hipLaunchKernelGGL(rank2_fused_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, A, n,
+                         k, V, tau, p, pv);
+    }
   }
   hipLaunchKernelGGL(tail_kernel, dim3(1), dim3(64), 0, s, A, n, d, e);
   // 2. eigenvalues

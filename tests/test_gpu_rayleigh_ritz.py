@@ -68,7 +68,7 @@ def test_shifted_cholqr3_fallback_ill_conditioned(ydtype):
     assert np.linalg.norm(Yh - Q @ (Q.T @ Yh)) <= 1e-12 * np.linalg.norm(Yh)
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 37, 200, 513])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 37, 200, 513])
 def test_syev_random_symmetric(n):
     print(f"syev n={n}", flush=True)
     torch, P = require_gpu()
