@@ -293,6 +293,8 @@ __device__ inline double start_value(int64_t i, int64_t j) {
 // alike, so their vectors stay independent combinations of the common eigenspace
 // instead of collapsing onto one eigenvector; an isolated eigenvalue at gap g
 // still converges by (delta/g)^3 in three steps.
+constexpr int IB = 8;   // rows per block of the pipelined triangular solves
+
 __global__ __launch_bounds__(64) void inverse_iteration_kernel(
     const double *d, const double *e, int64_t n, const double *lambda, const double *tnorm,
     double *Zt, double *dg, double *du, double *du2, double *dl, double *swp) {
@@ -329,28 +331,84 @@ __global__ __launch_bounds__(64) void inverse_iteration_kernel(
   }
   for (int it = 0; it < 3; ++it) {
     const double inv = 1.0 / sqrt(nrm);
-    // forward: row interchanges and multipliers (L y = P b)
+    // forward: row interchanges and multipliers (L y = P b).  Both solves run
+    // in blocks of IB rows whose operands are loaded one block ahead (rows
+    // clamped into range), so the memory latency is paid once per block and
+    // not once per row; every row is still loaded before it is overwritten.
+    const int64_t nf = n - 1;                 // elimination steps i = 0 .. n-2
     double cur = AT(Zt, 0) * inv;
-    for (int64_t i = 0; i + 1 < n; ++i) {
-      const double nxt = AT(Zt, i + 1) * inv;
-      double bi = cur, bn = nxt;
-      if (AT(swp, i) != 0.0) { bi = nxt; bn = cur; }
-      AT(Zt, i) = bi;
-      cur = bn - AT(dl, i) * bi;
+    {
+      double za[IB], sa[IB], la[IB], zb[IB], sb[IB], lb[IB];
+      auto fload = [&](int64_t i0, double (&z)[IB], double (&sw)[IB], double (&l)[IB]) {
+#pragma unroll
+        for (int t = 0; t < IB; ++t) {
+          const int64_t i = min(i0 + t, nf - 1);
+          z[t] = AT(Zt, i + 1);
+          sw[t] = AT(swp, i);
+          l[t] = AT(dl, i);
+        }
+      };
+      auto fstep = [&](int64_t i0, const double (&z)[IB], const double (&sw)[IB], const double (&l)[IB]) {
+#pragma unroll
+        for (int t = 0; t < IB; ++t) {
+          const int64_t i = i0 + t;
+          if (i < nf) {
+            const double nxt = z[t] * inv;
+            double bi = cur, bn = nxt;
+            if (sw[t] != 0.0) { bi = nxt; bn = cur; }
+            AT(Zt, i) = bi;
+            cur = bn - l[t] * bi;
+          }
+        }
+      };
+      if (nf > 0) fload(0, za, sa, la);
+      for (int64_t i0 = 0; i0 < nf; i0 += 2 * IB) {
+        if (i0 + IB < nf) fload(i0 + IB, zb, sb, lb);
+        fstep(i0, za, sa, la);
+        if (i0 + 2 * IB < nf) fload(i0 + 2 * IB, za, sa, la);
+        if (i0 + IB < nf) fstep(i0 + IB, zb, sb, lb);
+      }
     }
     AT(Zt, n - 1) = cur;
-    // backward: U x = y
+    // backward: U x = y, rows n-1 down to 0
     nrm = 0.0;
     double x1 = 0.0, x2 = 0.0;
-    for (int64_t i = n - 1; i >= 0; --i) {
-      double s = AT(Zt, i);
-      if (i + 1 < n) s -= AT(du, i) * x1;
-      if (i + 2 < n) s -= AT(du2, i) * x2;
-      const double xi = s / AT(dg, i);
-      AT(Zt, i) = xi;
-      nrm += xi * xi;
-      x2 = x1;
-      x1 = xi;
+    {
+      double ya[IB], ua[IB], va[IB], ga[IB], yb[IB], ub[IB], vb[IB], gb[IB];
+      auto bload = [&](int64_t i0, double (&y)[IB], double (&u1)[IB], double (&u2)[IB], double (&g)[IB]) {
+#pragma unroll
+        for (int t = 0; t < IB; ++t) {
+          const int64_t i = max(i0 - t, (int64_t)0);
+          y[t] = AT(Zt, i);
+          u1[t] = AT(du, i);
+          u2[t] = AT(du2, i);
+          g[t] = AT(dg, i);
+        }
+      };
+      auto bstep = [&](int64_t i0, const double (&y)[IB], const double (&u1)[IB], const double (&u2)[IB],
+                       const double (&g)[IB]) {
+#pragma unroll
+        for (int t = 0; t < IB; ++t) {
+          const int64_t i = i0 - t;
+          if (i >= 0) {
+            double s = y[t];
+            if (i + 1 < n) s -= u1[t] * x1;
+            if (i + 2 < n) s -= u2[t] * x2;
+            const double xi = s / g[t];
+            AT(Zt, i) = xi;
+            nrm += xi * xi;
+            x2 = x1;
+            x1 = xi;
+          }
+        }
+      };
+      bload(n - 1, ya, ua, va, ga);
+      for (int64_t i0 = n - 1; i0 >= 0; i0 -= 2 * IB) {
+        if (i0 - IB >= 0) bload(i0 - IB, yb, ub, vb, gb);
+        bstep(i0, ya, ua, va, ga);
+        if (i0 - 2 * IB >= 0) bload(i0 - 2 * IB, ya, ua, va, ga);
+        if (i0 - IB >= 0) bstep(i0 - IB, yb, ub, vb, gb);
+      }
     }
     if (!(nrm > 0.0) || !isfinite(nrm)) {  // fall back to a fresh start
       nrm = 0.0;
