@@ -134,6 +134,8 @@ __global__ __launch_bounds__(256) void rank2_fused_kernel(double *A, int64_t n, 
   }
 }
 
+constexpr int RB = 8;   // row elements loaded together in tridiag_step_kernel
+
 // Step k's rank-2 update fused with step k+1's reflector and product, so that
 // the trailing block is read and written once per step.  Row k+1 (row 0 of the
 // step-k trailing block, the source of reflector k+1) is only read: every
@@ -162,9 +164,22 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(double *A, int64_t n,
   const double *v = V + k * n + k + 1;                 // reflector k, v[0] = 1
   const double *x = A + (k + 1) * n + k + 1;           // row k+1 before the update
   const double w0 = p[0] - K * v[0];
-  for (int64_t j = 1 + threadIdx.x; j < m; j += 256) {
-    const double wj = p[j] - K * v[j];
-    vn[j - 1] = x[j] - (v[0] * wj + w0 * v[j]);
+  // The loops over a row load RB elements (clamped into range) before using
+  // any: one memory latency per RB elements rather than per element.
+  for (int64_t j0 = 1 + threadIdx.x; j0 < m; j0 += 256 * RB) {
+    double xj[RB], pj[RB], vj[RB];
+#pragma unroll
+    for (int t = 0; t < RB; ++t) {
+      const int64_t j = min(j0 + 256 * t, m - 1);
+      xj[t] = x[j];
+      pj[t] = p[j];
+      vj[t] = v[j];
+    }
+#pragma unroll
+    for (int t = 0; t < RB; ++t) {
+      const int64_t j = j0 + 256 * t;
+      if (j < m) vn[j - 1] = xj[t] - (v[0] * (pj[t] - K * vj[t]) + w0 * vj[t]);
+    }
   }
   __syncthreads();
   double t, scale, beta;
@@ -190,11 +205,24 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(double *A, int64_t n,
     const double vi = v[i], wi = p[i] - K * vi;
     double *row = A + (k + 1 + i) * n + k + 1;
     double acc = 0.0;
-    for (int64_t j = 1 + lane; j < m; j += 64) {
-      const double wj = p[j] - K * v[j];
-      const double a = row[j] - (vi * wj + wi * v[j]);
-      row[j] = a;
-      acc += a * vn[j - 1];
+    for (int64_t j0 = 1 + lane; j0 < m; j0 += 64 * RB) {
+      double aj[RB], pj[RB], vj[RB];
+#pragma unroll
+      for (int t = 0; t < RB; ++t) {
+        const int64_t j = min(j0 + 64 * t, m - 1);
+        aj[t] = row[j];
+        pj[t] = p[j];
+        vj[t] = v[j];
+      }
+#pragma unroll
+      for (int t = 0; t < RB; ++t) {
+        const int64_t j = j0 + 64 * t;
+        if (j < m) {
+          const double a = aj[t] - (vi * (pj[t] - K * vj[t]) + wi * vj[t]);
+          row[j] = a;
+          acc += a * vn[j - 1];
+        }
+      }
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
     const double pi = t * acc;
