@@ -116,6 +116,33 @@ def test_syev_closed_form_and_degenerate_spectra():
     assert np.max(np.abs(Z.cpu().numpy().T @ Z.cpu().numpy() - np.eye(5))) <= 1e-14
 
 
+@pytest.mark.slow
+def test_syev_two_launch_tridiagonalisation_above_8192():
+    """n = 8200: the reflector no longer fits the 64 KiB of LDS of the fused step, so the
+    product and the rank-2 update run as two launches per step.  The spectrum is fixed by
+    construction, S = H2 H1 diag(d) H1 H2 with two Householder reflections (built on the
+    GPU in FP64); the bounds are those of the n <= 513 cases scaled by sqrt(n / 513)."""
+    torch, P = require_gpu()
+    n = 8200
+    print(f"syev n={n} (two-launch tridiagonalisation)", flush=True)
+    rng = np.random.default_rng(11)
+    d = np.linspace(-3.0, 7.0, n)
+    S = torch.diag(_cuda(d))
+    for _ in range(2):
+        u = _cuda(rng.standard_normal(n))
+        u = u / torch.linalg.vector_norm(u)
+        Su = S @ u
+        S = S - 2 * torch.outer(u, Su) - 2 * torch.outer(Su, u) + 4 * (u @ Su) * torch.outer(u, u)
+    S = 0.5 * (S + S.T)
+    lam, Z = P.syev(S)
+    grow = (n / 513) ** 0.5
+    nrm = 7.0
+    assert float((lam.cpu() - torch.from_numpy(d)).abs().max()) <= 1e-13 * nrm * n ** 0.5
+    eye = torch.eye(n, dtype=torch.float64, device="cuda")
+    assert float((Z.T @ Z - eye).abs().max()) <= 1e-13 * grow
+    assert float((S @ Z - Z * lam).abs().max()) <= 1e-12 * nrm * grow
+
+
 def test_rotate_and_project():
     torch, P = require_gpu()
     Hc, Hb, X = make_case(8, 3, 40, seed=5)
