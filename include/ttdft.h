@@ -221,8 +221,10 @@ ttdft_status ttdft_cholqr2(const void *Y, int64_t ldy, ttdft_dtype y_dtype, int6
 size_t ttdft_project_workspace(const ttdft_bsr *H, int64_t n_vec);
 
 /*
- * Step 3 of Algorithm 1 (subspace projection, Sec. 4.3): A = Q^T (H Q),
- * written symmetrised as (A + A^T)/2.  H must be FP64.  Q: device FP64
+ * Step 3 of Algorithm 1 (subspace projection, Sec. 4.3): A = Q^T (H Q), which
+ * is symmetric because H is: the lower-triangular 128 x 128 tiles are formed
+ * and mirrored, and inside the diagonal tiles A_ij and A_ji are averaged, so A
+ * is written exactly symmetric.  H must be FP64.  Q: device FP64
  * 64*n_block_rows x n_vec (ldq).  A: device FP64 n_vec x n_vec (lda).  ASYNC.
  * Errors: NULL, SHAPE, DTYPE, WORKSPACE, ALIAS, HIP.
  */

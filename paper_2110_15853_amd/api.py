@@ -185,7 +185,7 @@ def cholqr2(Y: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:
 
 
 def project(H: BsrMatrix, Q: torch.Tensor) -> torch.Tensor:
-    """ttdft_project: (Q^T H Q + (Q^T H Q)^T)/2 in FP64 (step 3 of Algorithm 1)."""
+    """ttdft_project: Q^T H Q in FP64, exactly symmetric (step 3 of Algorithm 1)."""
     hs = H.c_struct()
     n = Q.shape[1]
     A = torch.empty((n, n), dtype=torch.float64, device=Q.device)

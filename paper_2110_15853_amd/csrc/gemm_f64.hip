@@ -156,7 +156,8 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_tn_kernel(
 }
 
 // C[i][j] = sum_s partial[s][i][j] in order s = 0, 1, ...; sym mirrors the
-// lower-triangular tiles; symmetrize writes (P + P^T)/2.
+// lower-triangular tiles; symmetrize writes (P + P^T)/2 (with sym: inside the
+// diagonal tiles, the only ones holding both P_ij and P_ji).
 __global__ __launch_bounds__(256) void reduce_splits_kernel(const double *__restrict__ partial,
                                                             int splits, int64_t n, double *C,
                                                             int64_t ldc, int sym, int symmetrize) {
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(256) void reduce_splits_kernel(const double *__rest
     if (sym && (i / BM) < (j / BN)) src = j * n + i;
     double v = 0.0;
     for (int s = 0; s < splits; ++s) v += partial[(int64_t)s * total + src];
-    if (symmetrize) {
+    if (symmetrize && (!sym || i / BM == j / BN)) {
       double u = 0.0;
       const int64_t srcT = j * n + i;
       for (int s = 0; s < splits; ++s) u += partial[(int64_t)s * total + srcT];

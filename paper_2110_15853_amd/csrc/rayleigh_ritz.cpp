@@ -144,7 +144,7 @@ struct ProjLayout {
 };
 ProjLayout proj_layout(int64_t rows, int64_t n) {
   ProjLayout L;
-  L.splits = gemm_tn_splits(rows, n, false);
+  L.splits = gemm_tn_splits(rows, n, true);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
   L.hq = take((size_t)rows * n * 8);
@@ -159,7 +159,9 @@ hipError_t project_enqueue(const ttdft_bsr &H, const double *Q, int64_t ldq, int
   double *HQ = (double *)(work + L.hq), *partial = (double *)(work + L.partial);
   hipError_t e = launch_cheb_step(H, Q, ldq, nullptr, 0, HQ, n, n, 1.0, 0.0, 0.0, TTDFT_F64, s);
   if (e != hipSuccess) return e;
-  return launch_gemm_tn_ex(Q, ldq, HQ, n, rows, n, A, lda, false, true, partial, L.splits, s);
+  // Q^T (H Q) is symmetric (H is): only its lower-triangular tiles are formed and
+  // mirrored; inside the diagonal tiles the two halves are averaged
+  return launch_gemm_tn_ex(Q, ldq, HQ, n, rows, n, A, lda, true, true, partial, L.splits, s);
 }
 
 struct RrLayout {

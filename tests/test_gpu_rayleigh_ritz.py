@@ -143,9 +143,10 @@ def test_syev_two_launch_tridiagonalisation_above_8192():
     assert float((S @ Z - Z * lam).abs().max()) <= 1e-12 * nrm * grow
 
 
-def test_rotate_and_project():
+@pytest.mark.parametrize("n", [40, 300])   # one diagonal tile; 3 x 3 tiles, ragged
+def test_rotate_and_project(n):
     torch, P = require_gpu()
-    Hc, Hb, X = make_case(8, 3, 40, seed=5)
+    Hc, Hb, X = make_case(8, 3, n, seed=5)
     Q = oracle.orth(X)
     Qb = P.to_blocked(_cuda(Q), Hb)
     Ad = P.project(Hb, Qb).cpu().numpy()
@@ -154,7 +155,7 @@ def test_rotate_and_project():
     assert normwise(Ad, ref) <= 1e-13
     assert np.array_equal(Ad, Ad.T)
     rng = np.random.default_rng(2)
-    Zq = rng.standard_normal((40, 40))
+    Zq = rng.standard_normal((n, n))
     Psi = P.from_blocked(P.rotate(Qb, _cuda(Zq)), Hb).cpu().numpy()
     assert normwise(Psi, Q @ Zq) <= 1e-14
 
