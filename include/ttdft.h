@@ -264,6 +264,9 @@ size_t ttdft_rayleigh_ritz_workspace(const ttdft_bsr *H, int64_t n_vec, ttdft_dt
 /*
  * Steps 2-5 of Algorithm 1 on a filtered block Y (the output of step 1):
  * X_F = Cholesky-QR2(Y); H_F = X_F^T H X_F; H_F Q = Q Lambda; Psi = X_F Q.
+ * X_F = Q1 M2 (first pass Q1 = Y M1, second-pass factor M2) is not formed:
+ * H_F = M2^T (Q1^T H Q1) M2 and Psi = Q1 (M2 Q), equal up to rounding; after a
+ * Cholesky breakdown the shifted Cholesky-QR3 forms X_F explicitly.
  * H must be FP64: the projection stays in FP64 whatever precision the filter
  * used.  Y: device 64*n_block_rows x n_vec of y_dtype.  lambda: device FP64
  * [n_vec], ascending.  Psi: device FP64 64*n_block_rows x n_vec (ldpsi).

@@ -70,15 +70,23 @@ QrLayout qr_layout(int64_t rows, int64_t n) {
 }
 
 // one Cholesky-QR pass: dst = src D^{-1} R^{-1}, with D^{-1} G D^{-1} + shift I = R^T R
-hipError_t cholqr_pass(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
-                       int64_t n, double shift, char *work, const QrLayout &L, hipStream_t s) {
+// the factor of one pass alone: M = D^{-1} R^{-1} (np x np, ld np) in work + L.m
+hipError_t cholqr_factor(const double *src, int64_t lds, int64_t rows, int64_t n, double shift,
+                         char *work, const QrLayout &L, hipStream_t s) {
   double *G = (double *)(work + L.g), *M = (double *)(work + L.m);
   double *chol = (double *)(work + L.chol), *partial = (double *)(work + L.partial);
   int *info = (int *)(work + L.info);
   hipError_t e;
   if ((e = launch_gemm_tn(src, lds, src, lds, rows, n, G, L.np, true, partial, L.splits, s))) return e;
-  if ((e = launch_chol_rinv(G, n, M, chol, info, s, shift)) != hipSuccess) return e;
-  return launch_gemm_nn_ex(src, lds, M, L.np, rows, n, n, 1.0, dst, ldd, true, s);
+  return launch_chol_rinv(G, n, M, chol, info, s, shift);
+}
+
+hipError_t cholqr_pass(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
+                       int64_t n, double shift, char *work, const QrLayout &L, hipStream_t s) {
+  hipError_t e = cholqr_factor(src, lds, rows, n, shift, work, L, s);
+  if (e != hipSuccess) return e;
+  return launch_gemm_nn_ex(src, lds, (const double *)(work + L.m), L.np, rows, n, n, 1.0, dst, ldd,
+                           true, s);
 }
 
 // FP64 copy of Y into Q when Y is not FP64 (the orthonormalisation is FP64)
@@ -105,6 +113,21 @@ hipError_t cholqr2_enqueue(const void *Y, int64_t ldy, ttdft_dtype ydt, int64_t 
   if (e != hipSuccess) return e;
   if ((e = cholqr_pass(src, lds, W, n, rows, n, 0.0, work, L, s)) != hipSuccess) return e;
   return cholqr_pass(W, n, Q, ldq, rows, n, 0.0, work, L, s);
+}
+
+// Cholesky-QR twice without the last product: Q1 = Y M1 is formed in Q, and the
+// second pass only factors Q1^T Q1 (its M2 is left in work + L.m), so that
+// X_F = Q1 M2 can be applied implicitly.  Enqueues only.
+hipError_t cholqr2_implicit_enqueue(const void *Y, int64_t ldy, ttdft_dtype ydt, int64_t rows,
+                                    int64_t n, double *Q, int64_t ldq, char *work,
+                                    const QrLayout &L, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_clear_ints((int *)(work + L.info), 4, s)) != hipSuccess) return e;
+  int64_t lds;   // a non-FP64 Y is cast into W, so that the product never runs in place
+  const double *src = fp64_source(Y, ldy, ydt, rows, n, (double *)(work + L.w), n, &lds, s, &e);
+  if (e != hipSuccess) return e;
+  if ((e = cholqr_pass(src, lds, Q, ldq, rows, n, 0.0, work, L, s)) != hipSuccess) return e;
+  return cholqr_factor(Q, ldq, rows, n, 0.0, work, L, s);
 }
 
 // Shifted Cholesky-QR3 (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa): a
@@ -167,7 +190,7 @@ hipError_t project_enqueue(const ttdft_bsr &H, const double *Q, int64_t ldq, int
 struct RrLayout {
   QrLayout qr;
   ProjLayout pj;
-  size_t xf, qr_off, pj_off, hf, zq, syev, total;
+  size_t xf, qr_off, pj_off, hf, zq, m2, syev, total;
 };
 RrLayout rr_layout(int64_t rows, int64_t n) {
   RrLayout L;
@@ -182,6 +205,7 @@ RrLayout rr_layout(int64_t rows, int64_t n) {
   L.pj_off = L.qr_off;
   L.hf = take((size_t)n * n * 8);
   L.zq = take((size_t)n * n * 8);
+  L.m2 = take((size_t)n * n * 8);
   L.syev = take(syev_work_bytes(n));
   L.total = off;
   return L;
@@ -324,17 +348,54 @@ ttdft_status ttdft_rayleigh_ritz(const ttdft_bsr *H, const void *Y, int64_t ldy,
     return failf(TTDFT_ERR_ALIAS, "buffers overlap");
   char *w = (char *)work;
   hipStream_t s = (hipStream_t)stream;
+  const int64_t n = n_vec;
   double *XF = (double *)(w + L.xf), *Hf = (double *)(w + L.hf), *Zq = (double *)(w + L.zq);
-  st = orthonormalise(Y, ldy, y_dtype, rows, n_vec, XF, n_vec, w + L.qr_off, L.qr, s, true);
-  if (st != TTDFT_OK) return st;
-  hipError_t e = project_enqueue(*H, XF, n_vec, n_vec, Hf, n_vec, w + L.pj_off, L.pj, s);
+  double *M2 = (double *)(w + L.m2);
+  // Cholesky-QR twice with X_F = Q1 M2 left implicit: XF holds Q1, the projected
+  // matrix is M2^T (Q1^T H Q1) M2 and the Ritz vectors are Q1 (M2 Z), which saves
+  // the rows x n x n product that would form X_F.  After a breakdown of the plain
+  // passes the shifted Cholesky-QR3 forms X_F explicitly (M2 = identity).
+  bool implicit = true;
+  hipError_t e = cholqr2_implicit_enqueue(Y, ldy, y_dtype, rows, n, XF, n, w + L.qr_off, L.qr, s);
+  if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: cholqr2 launch");
+  int col = qr_breakdown(w + L.qr_off, L.qr, s, &e);
+  if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: cholqr2");
+  if (col) {
+    implicit = false;
+    e = shifted_cholqr3_enqueue(Y, ldy, y_dtype, rows, n, XF, n, w + L.qr_off, L.qr, s);
+    if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: shifted cholqr3 launch");
+    col = qr_breakdown(w + L.qr_off, L.qr, s, &e);
+    if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: shifted cholqr3");
+    if (col) return failf(TTDFT_ERR_NOT_POSDEF, "Cholesky breakdown at column %d: block rank-deficient in FP64", col);
+  } else {
+    // M2 leaves the Cholesky-QR scratch, which the projection reuses
+    e = launch_cast(w + L.qr_off + L.qr.m, TTDFT_F64, L.qr.np, M2, TTDFT_F64, n, n, n, s);
+    if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: copy");
+  }
+  e = project_enqueue(*H, XF, n, n, Hf, n, w + L.pj_off, L.pj, s);
   if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: projection");
+  if (implicit) {
+    // Hf <- M2^T (Hf M2), exactly symmetric (lower tiles mirrored, diagonal tiles
+    // averaged); Zq is free until the eigensolve and holds Hf M2
+    const int splits = gemm_tn_splits(n, n, true);
+    if (splits > L.pj.splits) return failf(TTDFT_ERR_WORKSPACE, "internal: split-K scratch too small");
+    double *partial = (double *)(w + L.pj_off + L.pj.partial);
+    e = launch_gemm_nn_ex(Hf, n, M2, n, n, n, n, 1.0, Zq, n, true, s);
+    if (e == hipSuccess) e = launch_gemm_tn_ex(M2, n, Zq, n, n, n, Hf, n, true, true, partial, splits, s);
+    if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: projection transform");
+  }
   int info[2] = {0, 0};
-  e = run_syev(n_vec, Hf, n_vec, lambda, Zq, n_vec, w + L.syev, s, info);
+  e = run_syev(n, Hf, n, lambda, Zq, n, w + L.syev, s, info);
   if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: eigensolve");
   if (info[1]) return failf(TTDFT_ERR_NONFINITE, "non-finite value in the projected matrix");
   if (info[0]) return failf(TTDFT_ERR_NO_CONVERGENCE, "eigenvector block lost rank");
-  e = launch_gemm_nn_ex(XF, n_vec, Zq, n_vec, rows, n_vec, n_vec, 1.0, Psi, ldpsi, false, s);
+  const double *Zr = Zq;
+  if (implicit) {   // Hf (copied by the eigensolve) is free: M2 Z
+    e = launch_gemm_nn_ex(M2, n, Zq, n, n, n, n, 1.0, Hf, n, false, s);
+    if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: rotation factor");
+    Zr = Hf;
+  }
+  e = launch_gemm_nn_ex(XF, n, Zr, n, rows, n, n, 1.0, Psi, ldpsi, false, s);
   if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: rotation");
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz");

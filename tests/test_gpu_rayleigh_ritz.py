@@ -68,6 +68,32 @@ def test_shifted_cholqr3_fallback_ill_conditioned(ydtype):
     assert np.linalg.norm(Yh - Q @ (Q.T @ Yh)) <= 1e-12 * np.linalg.norm(Yh)
 
 
+@pytest.mark.parametrize("ydtype", ["f64", "f32"])
+def test_rayleigh_ritz_after_cholqr_breakdown(ydtype):
+    """A block with singular values down to 1e-12 breaks the plain Cholesky-QR passes;
+    the fused Rayleigh-Ritz then forms X_F explicitly by the shifted Cholesky-QR3.  The
+    span of such a block is fixed only to about u / 1e-12, so the checks are the
+    properties of the result: orthonormal Ritz vectors spanning Y, diagonal projection."""
+    torch, P = require_gpu()
+    n = 60
+    Hc, Hb, _ = make_case(8, 3, n, seed=7)
+    rng = np.random.default_rng(9)
+    U, _ = np.linalg.qr(rng.standard_normal((Hc.shape[0], n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    Y = (U * np.logspace(0, -12, n)) @ V.T
+    Yb = P.to_blocked(_cuda(Y), Hb)
+    if ydtype == "f32":
+        Yb = Yb.float()
+    Yh = P.from_blocked(Yb.double(), Hb).cpu().numpy()
+    lam, Psib = P.rayleigh_ritz(Hb, Yb)
+    lam, Psi = lam.cpu().numpy(), P.from_blocked(Psib, Hb).cpu().numpy()
+    hn = np.abs(np.linalg.eigvalsh(Hc.toarray())).max()
+    assert np.all(np.diff(lam) >= 0)
+    assert np.max(np.abs(Psi.T @ Psi - np.eye(n))) <= 1e-13
+    assert np.max(np.abs(Psi.T @ (Hc @ Psi) - np.diag(lam))) <= 1e-12 * hn
+    assert np.linalg.norm(Yh - Psi @ (Psi.T @ Yh)) <= 1e-12 * np.linalg.norm(Yh)
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 37, 200, 513])
 def test_syev_random_symmetric(n):
     print(f"syev n={n}", flush=True)
