@@ -498,8 +498,22 @@ __global__ __launch_bounds__(64) void wy_t_kernel(const double *G, const double 
   for (int j = 0; j < nb; ++j) {
     const double tj = tau[k0 + j];
     double s = 0.0;
-    if (i < j)
-      for (int l = i; l < j; ++l) s += sT[i][l] * sG[l][j];
+    if (i < j) {
+      // operands of 8 terms are read before any is used (one LDS latency per 8);
+      // terms past j - 1 read in-range entries and are masked out
+      for (int l0 = i; l0 < j; l0 += 8) {
+        double a[8], g[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int l = min(l0 + u, 63);
+          a[u] = sT[i][l];
+          g[u] = sG[l][j];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (l0 + u < j) s += a[u] * g[u];
+      }
+    }
     __syncthreads();
     if (i < j) sT[i][j] = -tj * s;
     if (i == j) sT[j][j] = tj;
