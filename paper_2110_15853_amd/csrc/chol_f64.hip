@@ -74,21 +74,23 @@ __global__ void gram_scale_kernel(double *G, int64_t n, int64_t np, const double
   }
 }
 
-// Factor the diagonal block p with one wave; write L_pp (lower) into G and
-// L_pp^{-1} into X.  The block sits in LDS row-major; step j (a rolled loop):
-// lane i > j forms l_ij = a_ij / sqrt(a_jj) in place, then for every k > j lane
-// i applies a_ik -= l_ij l_kj, l_kj read with the same address by every lane.  A single wave executes its LDS operations in order, so no barrier is
-// needed between the steps.  Then lane c holds column c of the identity in
-// registers and eliminates with the factor's columns: x_j = b_j / l_jj,
-// b_k -= l_kj x_j (k > j), leaving column c of L^{-1} (unrolled; a scheduling
-// barrier between steps bounds the register use).
-__global__ __launch_bounds__(64) void potrf_diag_kernel(double *G, int64_t np, int p, double *X,
-                                                        int *info) {
+// Factor the diagonal block p with four waves; write L_pp (lower) into G and
+// L_pp^{-1} into X.  The block sits in LDS row-major, lane i of every wave on
+// row i.  Step j (a rolled loop): lanes i > j of wave 0 form l_ij = a_ij /
+// sqrt(a_jj) in place; after a barrier every wave applies a_ik -= l_ij l_kj to
+// the columns k > j it owns (wave w: columns 16w .. 16w+15), l_kj read with the
+// same address by every lane, and a second barrier closes the step.  Then wave 0
+// has lane c hold column c of the identity in registers and eliminate with the
+// factor's columns: x_j = b_j / l_jj, b_k -= l_kj x_j (k > j), leaving column c
+// of L^{-1} (unrolled; a scheduling barrier between steps bounds the register
+// use).
+__global__ __launch_bounds__(256) void potrf_diag_kernel(double *G, int64_t np, int p, double *X,
+                                                         int *info) {
   if (*info) return;
   __shared__ double La[T][T + 1];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double *Gp = G + (int64_t)p * T * np + (int64_t)p * T;
-  for (int r = 0; r < T; ++r) La[r][lane] = Gp[r * np + lane];   // coalesced rows
+  for (int r = wv; r < T; r += 4) La[r][lane] = Gp[r * np + lane];   // coalesced rows
   __syncthreads();
   int bad = 0;
   for (int j = 0; j < T; ++j) {
@@ -98,17 +100,16 @@ __global__ __launch_bounds__(64) void potrf_diag_kernel(double *G, int64_t np, i
       piv = 1.0;
     }
     const double ljj = sqrt(piv);
-    double l = 0.0;
-    if (lane > j) {
-      l = La[lane][j] / ljj;
-      La[lane][j] = l;
+    if (wv == 0) {
+      if (lane > j) La[lane][j] = La[lane][j] / ljj;
+      if (lane == j) La[j][j] = ljj;
     }
-    if (lane == j) La[j][j] = ljj;
-    // trailing update in chunks of 8 columns: all reads of a chunk, then the
-    // products (kept only for columns k > j; entries above the diagonal are
-    // updated too but never read), then the writes -- one LDS round trip per
-    // chunk, no per-column branch
-    for (int kc = (j + 1) & ~7; kc < T; kc += 8) {
+    __syncthreads();
+    // trailing update of this wave's 16 columns in chunks of 8: all reads of a
+    // chunk, then the products (kept only for columns k > j; entries above the
+    // diagonal are updated too but never read), then the writes
+    const double l = lane > j ? La[lane][j] : 0.0;
+    for (int kc = max(16 * wv, (j + 1) & ~7); kc < 16 * wv + 16; kc += 8) {
       double lk[8], ak[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -123,27 +124,29 @@ __global__ __launch_bounds__(64) void potrf_diag_kernel(double *G, int64_t np, i
 #pragma unroll
       for (int u = 0; u < 8; ++u) La[lane][kc + u] = ak[u];
     }
+    __syncthreads();
   }
-  __syncthreads();
   if (bad) {
-    if (lane == 0) atomicCAS(info, 0, bad);
+    if (threadIdx.x == 0) atomicCAS(info, 0, bad);
     return;
   }
-  double b[T];
+  if (wv == 0) {
+    double b[T];
 #pragma unroll
-  for (int k = 0; k < T; ++k) b[k] = k == lane ? 1.0 : 0.0;
+    for (int k = 0; k < T; ++k) b[k] = k == lane ? 1.0 : 0.0;
 #pragma unroll
-  for (int j = 0; j < T; ++j) {
-    const double x = b[j] / La[j][j];
-    b[j] = x;
+    for (int j = 0; j < T; ++j) {
+      const double x = b[j] / La[j][j];
+      b[j] = x;
 #pragma unroll
-    for (int k = j + 1; k < T; ++k) b[k] = fma(-La[k][j], x, b[k]);
-    __builtin_amdgcn_sched_barrier(0);
+      for (int k = j + 1; k < T; ++k) b[k] = fma(-La[k][j], x, b[k]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    double *Xp = X + (int64_t)p * T * np + (int64_t)p * T;
+#pragma unroll
+    for (int i = 0; i < T; ++i) Xp[(int64_t)i * np + lane] = b[i];   // lane = column: coalesced
   }
-  double *Xp = X + (int64_t)p * T * np + (int64_t)p * T;
-#pragma unroll
-  for (int i = 0; i < T; ++i) Xp[(int64_t)i * np + lane] = b[i];   // lane = column: coalesced
-  for (int r = 0; r < T; ++r) Gp[r * np + lane] = lane <= r ? La[r][lane] : 0.0;
+  for (int r = wv; r < T; r += 4) Gp[r * np + lane] = lane <= r ? La[r][lane] : 0.0;
 }
 
 // L_ip = A_ip L_pp^{-T} for every block row i > p (one work-group each)
@@ -224,7 +227,7 @@ hipError_t launch_chol_rinv(double *G, int64_t n, double *Rinv, double *scratch,
   hipLaunchKernelGGL(gram_scale_diag_kernel, dim3(grid_for(np)), dim3(256), 0, s, G, n, np, d, info);
   hipLaunchKernelGGL(gram_scale_kernel, dim3(grid_for(np * np)), dim3(256), 0, s, G, n, np, d, X, shift);
   for (int p = 0; p < nb; ++p) {
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(64), 0, s, G, np, p, X, info);
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, s, G, np, p, X, info);
     if (p + 1 < nb) {
       hipLaunchKernelGGL(trsm_panel_kernel, dim3(nb - p - 1), dim3(256), 0, s, G, np, p, X, info);
       const int pairs = (nb - p - 1) * (nb - p) / 2;
