@@ -3,10 +3,14 @@
 One step = one pass of the hot path over the resident synthetic block: the
 degree-m Chebyshev filter (m fused BSR-SpMM + recurrence launches) followed,
 when available, by the FP64 Rayleigh-Ritz step (Cholesky-QR twice, X^T H X,
-dense eigensolve, rotation).  Prints ONE JSON line.
+dense eigensolve, rotation).  Prints ONE JSON line.  Beside the timed steps it
+reports the occupancies and density on the step's Ritz pairs, the filter's
+adjoint on the adjoint workload, the reduced-precision filters against FP64 and
+the CPU oracle's rate.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--precision f64|f32|bf16] [--no-cpu-baseline] [--no-rr]
+                    [--no-mixed] [--no-adjoint] [--solve] [--calib-copy]
 """
 from __future__ import annotations
 
@@ -134,12 +138,62 @@ def density_report(P, torch, H, lam, psi, cfg):
             times[k].append(ev[i].elapsed_time(ev[j]))
     tr = float((Pv * H.vals).sum())
     want = 2.0 * float((f * lam).sum())
-    # the sampled product issues 2 * 4096 * n flop per stored tile
+    # the sampled product issues 2 * 256 * n flop per 16 x 16 block of a stored tile
+    # that holds a pattern entry (the other blocks are skipped)
+    m = H.mask.view(H.n_tiles, 4, 16).cpu().numpy().view(np.uint64)
+    rows_or = np.bitwise_or.reduce(m, axis=2)                       # [tile, row block]
+    live = sum(int(np.count_nonzero((rows_or >> np.uint64(16 * jb)) & np.uint64(0xFFFF)))
+               for jb in range(4))
     dm_s = float(np.median(times["density_matrix_ms"])) / 1e3
     return {"n_electrons": ne, "kT_hartree": P.KT_500K_HARTREE, "mu": mu,
             **{k: round(float(np.median(v)), 3) for k, v in times.items()},
-            "density_matrix_issued_tflops": round(2.0 * 4096 * cfg.n * H.n_tiles / dm_s / 1e12, 2),
+            "density_matrix_issued_tflops": round(2.0 * 256 * cfg.n * live / dm_s / 1e12, 2),
+            "density_matrix_live_blocks": live, "density_matrix_blocks": 16 * H.n_tiles,
             "sum_rho": float(rho.sum()), "trace_PH": tr, "two_sum_f_lambda": want}
+
+
+def adjoint_report(P, torch, workload):
+    """The filter's adjoint on the adjoint workload (r = 40, h = 3, 512 vectors,
+    m = 16, loss sum(w * Y) with w ~ N(0,1)): the forward filter and the backward
+    with every iterate stored and with a checkpoint every 4 steps, FP64 and FP32,
+    each timed with HIP events (median of 3).  Algorithmic work of the backward:
+    m reverse products and m products sampled on the pattern, 4 m nnz n flop."""
+    cfg = workload.CONFIGS["lattice40_h3_n512_m16"]
+    ip, ix, d, N = workload.lattice_hamiltonian(cfg.r, cfg.h, cfg.seed)
+    nnz = int(len(ix))
+    X = torch.from_numpy(workload.gaussian_block(N, cfg.n, cfg.seed)).cuda()
+    W = torch.from_numpy(workload.gaussian_block(N, cfg.n, cfg.seed, stream="W")).cuda()
+    H64 = P.bsr_build(ip, ix, d, cfg.r, dtype=torch.float64, device="cuda")
+    out = {"workload": cfg.name, "N": N, "n_vec": cfg.n, "m": cfg.m, "nnz": nnz}
+    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        H = H64 if dt == torch.float64 else P.bsr_astype(H64, dt)
+        Xb, Wb = P.to_blocked(X.to(dt), H), P.to_blocked(W.to(dt), H)
+        runs = {
+            "forward_ms": lambda: P.cheb_filter(H, Xb, cfg.m, cfg.a, cfg.b, cfg.a0),
+            "backward_store_all_ms": lambda: P.cheb_filter_backward(H, Xb, Wb, cfg.m, cfg.a, cfg.b,
+                                                                    cfg.a0, ckpt_every=0),
+            "backward_ckpt4_ms": lambda: P.cheb_filter_backward(H, Xb, Wb, cfg.m, cfg.a, cfg.b,
+                                                                cfg.a0, ckpt_every=4),
+        }
+        r = {}
+        for key, f in runs.items():
+            f()
+            torch.cuda.synchronize()
+            ms = []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                f()
+                e1.record()
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            r[key] = round(float(np.median(ms)), 3)
+        r["forward_alg_tflops"] = round(2.0 * cfg.m * nnz * cfg.n / r["forward_ms"] / 1e9, 2)
+        r["backward_alg_tflops"] = round(4.0 * cfg.m * nnz * cfg.n / r["backward_store_all_ms"] / 1e9, 2)
+        out[name] = r
+        del H, Xb, Wb
+        torch.cuda.empty_cache()
+    return out
 
 
 def run_large(args, P, torch, workload):
@@ -279,6 +333,8 @@ def main():
     ap.add_argument("--max-passes", type=int, default=40)
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the reduced-precision filters and their Ritz-value errors")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint report (forward and backward on the adjoint workload)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain device copy of the X block (known bytes) before the timed "
                          "steps, to scale hardware byte counters")
@@ -416,6 +472,9 @@ def main():
     if do_rr and args.precision == "f64":
         out["density"] = density_report(P, torch, H, rr_out["lam"], rr_out["psi"], cfg)
         log(f"density: {out['density']}")
+    if not args.no_adjoint and args.precision == "f64" and do_rr:
+        out["adjoint"] = adjoint_report(P, torch, workload)
+        log(f"adjoint: {out['adjoint']}")
     if not args.no_mixed and args.precision == "f64" and do_rr:
         del rr_work, work
         rr_out.clear()

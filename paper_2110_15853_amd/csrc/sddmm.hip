@@ -65,6 +65,20 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
 
   typename O::acc_t acc[4];
   for (int j = 0; j < 4; ++j) acc[j] = typename O::acc_t{0, 0, 0, 0};
+  // 16x16 output blocks of this wave (rows 16w .., columns 16 jb ..) holding no
+  // pattern entry are written as 0 below whatever they hold: skip their products
+  unsigned live = 0xFu;
+  if (mask) {
+    const uint64_t mw = lane < 16 ? mask[t * 64 + 16 * w + lane] : 0ull;
+    unsigned lo32 = (unsigned)mw, hi32 = (unsigned)(mw >> 32);
+    for (int o = 8; o > 0; o >>= 1) {
+      lo32 |= __shfl_xor(lo32, o, 64);
+      hi32 |= __shfl_xor(hi32, o, 64);
+    }
+    live = ((lo32 & 0xFFFFu) ? 1u : 0u) | ((lo32 >> 16) ? 2u : 0u) |
+           ((hi32 & 0xFFFFu) ? 4u : 0u) | ((hi32 >> 16) ? 8u : 0u);
+    live = __builtin_amdgcn_readfirstlane(live);        // lane 0 holds the OR of rows 0..15
+  }
 
   for (int64_t c0 = 0; c0 < n_vec; c0 += BK) {
 #pragma unroll
@@ -78,13 +92,16 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
       sB[kk][r] = in ? widen<TC, TX>(Br[(int64_t)r * ldb + c]) : TC(0);
     }
     __syncthreads();
+    TC a[BK / 4];
 #pragma unroll
-    for (int kq = 0; kq < BK; kq += 4) {
-      const TC a = sA[kq + (lane >> 4)][16 * w + (lane & 15)];
+    for (int kq = 0; kq < BK; kq += 4) a[kq / 4] = sA[kq + (lane >> 4)][16 * w + (lane & 15)];
 #pragma unroll
-      for (int jb = 0; jb < 4; ++jb) {
+    for (int jb = 0; jb < 4; ++jb) {
+      if (!((live >> jb) & 1u)) continue;
+#pragma unroll
+      for (int kq = 0; kq < BK; kq += 4) {
         const TC b = sB[kq + (lane >> 4)][16 * jb + (lane & 15)];
-        acc[jb] = O::mma(a, b, acc[jb]);
+        acc[jb] = O::mma(a[kq / 4], b, acc[jb]);
       }
     }
     __syncthreads();
