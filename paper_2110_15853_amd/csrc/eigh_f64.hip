@@ -2,8 +2,11 @@
 // Algorithm 1 (Sec. 3.4):  H_F Z = Z diag(lambda), lambda ascending.
 //
 //  1. Householder tridiagonalisation H_F = Q T Q^T, one reflector per column
-//     (reflector, symmetric product, correction vector, rank-2 update);
-//  2. eigenvalues of T by bisection on Sturm counts, one eigenvalue per thread;
+//     (reflector, symmetric product, correction vector, rank-2 update), the
+//     rank-2 update of each step fused with the next step's reflector and
+//     product (one launch per step);
+//  2. eigenvalues of T by multisection on Sturm counts, one wave per eigenvalue
+//     (64 points per step);
 //  3. eigenvectors of T by inverse iteration (tridiagonal LU with partial
 //     pivoting), one eigenvector per thread, from pseudo-random starts;
 //  4. Cholesky-QR twice on the eigenvector block (matrix-core GEMMs), which

@@ -1,7 +1,9 @@
 // Host side of steps 2-5 of Algorithm 1 (Sec. 3.4), all in FP64 on the GPU:
 // Cholesky-QR twice with column scaling, the projection X_F^T (H X_F) with the
 // fused BSR kernel and a matrix-core GEMM, the dense eigensolve and the
-// rotation Psi = X_F Q.  Validation runs before any device work.
+// rotation Psi = X_F Q.  The fused entry point keeps X_F = Q1 M2 implicit (the
+// projection and the rotation go through the second pass's factor M2).
+// Validation runs before any device work.
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
