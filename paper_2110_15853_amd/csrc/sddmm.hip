@@ -6,8 +6,10 @@
 // entry (i, j) at 64*(4*(j/4) + i/16) + 16*(j%4) + i%16).  An optional weight
 // per vector c multiplies Abar[.][c] (the density matrix on the pattern of H is
 // this product with weights 2 f_c and Abar = Yk = Psi).  One work-group owns one tile and sweeps the vector
-// dimension in 32-wide panels, both operands staged transposed in LDS
-// ([vector][row]) so every matrix-core operand read is 16 consecutive values.
+// dimension in 16-wide panels, both operands staged transposed in LDS
+// ([vector][row]) so every matrix-core operand read is 16 consecutive values;
+// the panels are double-buffered, the next one loaded into registers while the
+// current one is contracted (one barrier per panel).
 // FP64 inputs use the f64 16x16x4 op; FP32 and BF16 inputs accumulate in FP32
 // on the f32 16x16x4 op.  Each tile is written by one work-group in a fixed
 // order, so accumulation over the degree steps is deterministic.
@@ -19,7 +21,7 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int BK = 32, THREADS = 256;
+constexpr int BK = 16, THREADS = 256;
 
 template <typename TC> struct Op;
 template <> struct Op<double> {
@@ -49,8 +51,8 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
     int64_t n_vec, TC coef, TC *__restrict__ dH, const uint64_t *__restrict__ mask,
     int accumulate, const double *__restrict__ colw) {
   using O = Op<TC>;
-  __shared__ TC sA[BK][64 + 1];
-  __shared__ TC sB[BK][64 + 1];
+  __shared__ TC sA[2][BK][64 + 1];
+  __shared__ TC sB[2][BK][64 + 1];
   const int64_t t = blockIdx.x;
   // block row of tile t: the last B with rowptr[B] <= t (binary search)
   int64_t lo = 0, hi = n_block_rows;
@@ -81,29 +83,45 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
     live = __builtin_amdgcn_readfirstlane(live);        // lane 0 holds the OR of rows 0..15
   }
 
-  for (int64_t c0 = 0; c0 < n_vec; c0 += BK) {
+  // panels of BK vectors, double-buffered in LDS; the next panel is loaded into
+  // registers while the current one is contracted (columns past n_vec read a
+  // clamped, in-range column and are stored as 0)
+  constexpr int Q = BK * 64 / THREADS;
+  TC ra[Q], rb[Q];
+  auto load = [&](int64_t c0) {
 #pragma unroll
-    for (int q = 0; q < BK * 64 / THREADS; ++q) {
+    for (int q = 0; q < Q; ++q) {
       const int idx = tid + THREADS * q;
       const int r = idx / BK, kk = idx % BK;     // consecutive threads walk the vector index
-      const int64_t c = c0 + kk;
-      const bool in = c < n_vec;
-      const TC wa = (in && colw) ? (TC)colw[c] : TC(1);
-      sA[kk][r] = in ? wa * widen<TC, TX>(Ar[(int64_t)r * lda + c]) : TC(0);
-      sB[kk][r] = in ? widen<TC, TX>(Br[(int64_t)r * ldb + c]) : TC(0);
+      const int64_t c = c0 + kk, cc = min(c, n_vec - 1);
+      const TC wa = colw ? (TC)colw[cc] : TC(1);
+      const TC av = wa * widen<TC, TX>(Ar[(int64_t)r * lda + cc]);
+      const TC bv = widen<TC, TX>(Br[(int64_t)r * ldb + cc]);
+      ra[q] = c < n_vec ? av : TC(0);
+      rb[q] = c < n_vec ? bv : TC(0);
     }
-    __syncthreads();
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int idx = tid + THREADS * q;
+      const int r = idx / BK, kk = idx % BK;
+      sA[buf][kk][r] = ra[q];
+      sB[buf][kk][r] = rb[q];
+    }
+  };
+  auto contract = [&](int buf) {
     if constexpr (sizeof(TC) == 8) {
       // FP64: the products dominate, so the blocks without pattern entries are skipped
       TC a[BK / 4];
 #pragma unroll
-      for (int kq = 0; kq < BK; kq += 4) a[kq / 4] = sA[kq + (lane >> 4)][16 * w + (lane & 15)];
+      for (int kq = 0; kq < BK; kq += 4) a[kq / 4] = sA[buf][kq + (lane >> 4)][16 * w + (lane & 15)];
 #pragma unroll
       for (int jb = 0; jb < 4; ++jb) {
         if (!((live >> jb) & 1u)) continue;
 #pragma unroll
         for (int kq = 0; kq < BK; kq += 4) {
-          const TC b = sB[kq + (lane >> 4)][16 * jb + (lane & 15)];
+          const TC b = sB[buf][kq + (lane >> 4)][16 * jb + (lane & 15)];
           acc[jb] = O::mma(a[kq / 4], b, acc[jb]);
         }
       }
@@ -112,15 +130,26 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
       // measured faster than the skipping one
 #pragma unroll
       for (int kq = 0; kq < BK; kq += 4) {
-        const TC a = sA[kq + (lane >> 4)][16 * w + (lane & 15)];
+        const TC a = sA[buf][kq + (lane >> 4)][16 * w + (lane & 15)];
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb) {
-          const TC b = sB[kq + (lane >> 4)][16 * jb + (lane & 15)];
+          const TC b = sB[buf][kq + (lane >> 4)][16 * jb + (lane & 15)];
           acc[jb] = O::mma(a, b, acc[jb]);
         }
       }
     }
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t c0 = 0; c0 < n_vec; c0 += BK) {
+    const bool more = c0 + BK < n_vec;
+    if (more) load(c0 + BK);
+    contract(buf);
+    if (more) store(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 
   TC *out = dH + t * kTileElems;
