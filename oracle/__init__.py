@@ -15,7 +15,7 @@ from .chfsi import (  # noqa: F401
     chebyshev_T,
     sigma_sequence,
     cheb_filter,
-    cheb_filter_alg1,
+    cheb_filter_scaled,
     cheb_filter_adjoint,
     orth,
     cholqr2,

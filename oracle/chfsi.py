@@ -76,22 +76,34 @@ def cheb_filter(H, X, m: int, a: float, b: float, a0: float):
     return z / chebyshev_T(m, tau)
 
 
-def cheb_filter_alg1(H, X, m: int, a: float, b: float, a0: float):
-    """Step 1 of Algorithm 1 in the paper's order and notation (sigma-scaled
-    three-term recurrence); returns the last filtered block X-tilde."""
+def cheb_filter_scaled(H, X, m: int, a: float, b: float, a0: float):
+    """The filtered block formed through scaled iterates, the way the filter of
+    Sec. 3.4 keeps its intermediate blocks of moderate size.
+
+    The scaled iterate is Y_k = T_k(Hs) X / t_k with Hs = (H - cI)/e and
+    t_j = T_j(tau), so Y_0 = X and Y_1 = Hs X / tau.  Dividing the defining
+    relation T_{k+1}(Hs) = 2 Hs T_k(Hs) - T_{k-1}(Hs) by t_{k+1} gives
+
+        Y_{k+1} = 2 (t_k / t_{k+1}) Hs Y_k - (t_{k-1} / t_{k+1}) Y_{k-1}.
+
+    The coefficients here are ratios of Chebyshev values taken from
+    chebyshev_T; Algorithm 1 obtains the same ratios by its sigma recursion
+    (sigma_k = t_{k-1} / t_k).  The last iterate Y_m equals cheb_filter's
+    result up to rounding.
+    """
     if m < 1:
         raise ValueError("degree m must be >= 1")
-    e, c, _ = filter_parameters(a, b, a0)
+    e, c, tau = filter_parameters(a, b, a0)
     X = np.asarray(X, dtype=np.float64)
-    sigma = e / (a0 - c)
-    sigma1 = sigma
-    gamma = 2.0 / sigma1
-    Xt = (sigma1 / e) * (H @ X - c * X)
-    for _ in range(2, m + 1):
-        sigma2 = 1.0 / (gamma - sigma)
-        Xnew = (2.0 * sigma2 / e) * (H @ Xt - c * Xt) - sigma * sigma2 * X
-        X, Xt, sigma = Xt, Xnew, sigma2
-    return Xt
+    t = [float(chebyshev_T(j, tau)) for j in range(m + 1)]
+
+    def hs(V):
+        return (H @ V - c * V) / e
+
+    y_prev, y = X, hs(X) / t[1]
+    for k in range(1, m):
+        y_prev, y = y, (2.0 * t[k] / t[k + 1]) * hs(y) - (t[k - 1] / t[k + 1]) * y_prev
+    return y
 
 
 def cheb_filter_adjoint(H, X, dY, m: int, a: float, b: float, a0: float,

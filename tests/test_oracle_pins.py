@@ -80,17 +80,17 @@ def test_filter_matches_spectral_closed_form(r, h, m):
     X = workload.gaussian_block(N, 6, 1)
     lam, V = np.linalg.eigh(H.toarray())
     ref = V @ (p_of(lam, m)[:, None] * (V.T @ X))
-    for fn in (oracle.cheb_filter, oracle.cheb_filter_alg1):
+    for fn in (oracle.cheb_filter, oracle.cheb_filter_scaled):
         Y = fn(H, X, m, A, B, A0)
         assert np.linalg.norm(Y - ref) / np.linalg.norm(ref) < 1e-13
 
 
-def test_filter_config1_alg1_vs_definition():
+def test_filter_config1_scaled_vs_definition():
     ip, ix, d, N = workload.lattice_hamiltonian(20, 3, 0)
     H = oracle.csr_from_arrays(ip, ix, d, N)
     X = workload.gaussian_block(N, 8, 0)
     Y1 = oracle.cheb_filter(H, X, 10, A, B, A0)
-    Y2 = oracle.cheb_filter_alg1(H, X, 10, A, B, A0)
+    Y2 = oracle.cheb_filter_scaled(H, X, 10, A, B, A0)
     assert np.linalg.norm(Y1 - Y2) / np.linalg.norm(Y1) < 1e-14
 
 
@@ -209,7 +209,7 @@ def test_adjoint_dx_is_filter_of_weights(m):
     W = workload.gaussian_block(N, 3, 10, stream="W")
     dX, _ = oracle.cheb_filter_adjoint(H, X, W, m, A, B, A0)
     # p(H) is symmetric for symmetric H, so dX = p(H) W
-    ref = oracle.cheb_filter_alg1(H, W, m, A, B, A0)
+    ref = oracle.cheb_filter_scaled(H, W, m, A, B, A0)
     np.testing.assert_allclose(dX, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
