@@ -282,7 +282,7 @@ def run_solve(args, P, torch, workload):
     n_conv = int(0.8 * cfg.n)
     t1 = time.perf_counter()
     lam, Psi, res, hist = P.chfsi_solve(Hf, H64, Xb, cfg.m, tol, n_conv=n_conv, max_iter=args.max_passes,
-                                        lanczos_k=40, timed=True)
+                                        lanczos_k=40)
     torch.cuda.synchronize()
     total = time.perf_counter() - t1
     done = [h for h in hist if not h.get("rank_deficient")]

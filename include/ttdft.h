@@ -27,6 +27,10 @@
  *   errors (TTDFT_ERR_HIP); the others synchronise the stream before returning.
  * - A thread-local message describing the last error is available from
  *   ttdft_last_error().
+ * - Blocks multiplied by H (the filter's iterates, the projection's Q, the
+ *   residuals' Psi) are addressed by the step kernel with 32-bit byte offsets
+ *   inside 64-row panels: 64 * ld * element size must be at most 2^31 - 1
+ *   (ld <= 4,194,303 for FP64), else TTDFT_ERR_SHAPE.
  */
 #ifndef TTDFT_H
 #define TTDFT_H
@@ -105,6 +109,17 @@ typedef struct {
  */
 ttdft_status ttdft_bsr_plan(int32_t r, const int64_t *rowptr, const int32_t *col,
                             int64_t *n_block_rows, int64_t *n_tiles);
+
+/*
+ * Size query with an explicit tile extent: the number of stored tiles of the
+ * blk x blk x blk lattice blocking of the same natural-order CSR (host arrays
+ * as for ttdft_bsr_plan).  The kernels are built for blk = 4 (64-row tiles
+ * matching the 16x16x4 matrix-core fragments); any other blk returns
+ * TTDFT_ERR_SHAPE.  n_tiles_out: host.  The number of block rows is
+ * ceil(r/4)^3.  Errors: as ttdft_bsr_plan.
+ */
+ttdft_status ttdft_bsr_build_size(int32_t r, int32_t blk, const int64_t *rowptr, const int32_t *col,
+                                  int64_t *n_tiles_out);
 
 /*
  * Builds the lattice-blocked BSR arrays (all host buffers, caller-allocated
@@ -211,7 +226,8 @@ size_t ttdft_cholqr2_workspace(int64_t n_rows, int64_t n_vec, ttdft_dtype y_dtyp
  * they must not overlap.  Requires n_rows >= n_vec.  Synchronises the stream
  * (a breakdown must be reported).
  * Errors: NULL, SHAPE, DTYPE, WORKSPACE, ALIAS, NOT_POSDEF (a non-positive
- * pivot: Y numerically rank-deficient in FP64), HIP.
+ * pivot: Y numerically rank-deficient in FP64), NONFINITE (Y holds a NaN or
+ * Inf), HIP.
  */
 ttdft_status ttdft_cholqr2(const void *Y, int64_t ldy, ttdft_dtype y_dtype, int64_t n_rows,
                            int64_t n_vec, double *Q, int64_t ldq, void *work,
@@ -272,7 +288,8 @@ size_t ttdft_rayleigh_ritz_workspace(const ttdft_bsr *H, int64_t n_vec, ttdft_dt
  * [n_vec], ascending.  Psi: device FP64 64*n_block_rows x n_vec (ldpsi).
  * Synchronises the stream.
  * Errors: NULL, SHAPE, DTYPE, WORKSPACE, ALIAS, NOT_POSDEF, NO_CONVERGENCE,
- * NONFINITE, HIP.
+ * NONFINITE (Y holds a NaN or Inf, or the projected matrix a non-finite
+ * value), HIP.
  */
 ttdft_status ttdft_rayleigh_ritz(const ttdft_bsr *H, const void *Y, int64_t ldy,
                                  ttdft_dtype y_dtype, int64_t n_vec, double *lambda,
@@ -281,33 +298,30 @@ ttdft_status ttdft_rayleigh_ritz(const ttdft_bsr *H, const void *Y, int64_t ldy,
 
 /* ---------------------------------------------------------------- spectrum bound for [a, b] */
 
-/* Bytes of workspace ttdft_lanczos_upper_bound needs for k steps. */
+/* Bytes of workspace ttdft_lanczos_bounds needs for k steps. */
 size_t ttdft_lanczos_workspace(const ttdft_bsr *H, int32_t k);
 
 /*
- * Estimate of the upper end of the spectrum of H, for the upper bound b of the
- * unwanted interval of the Chebyshev filter (Sec. 3.4): k steps of the Lanczos
- * process from a seeded random start vector (zero on padding rows):
- *   bound[0] = theta_max, the largest eigenvalue of the k x k Lanczos tridiagonal
- *              (a lower estimate of the top of the spectrum),
- *   bound[1] = theta_max + |beta_{k+1} s_k|, s_k the last component of its
- *              eigenvector (theta_max plus its Ritz residual: the usual estimate),
- *   bound[2] = theta_max + beta_{k+1} (safeguarded, pessimistic).
+ * Estimates of both ends of the spectrum of H, for the bounds of the Chebyshev
+ * filter (Sec. 3.4 needs an upper bound b of the unwanted spectrum and a
+ * scaling point a0 below the wanted one): k steps of the Lanczos process from
+ * a seeded random start vector (zero on padding rows), then
+ *   bounds[0] = theta_max, the largest eigenvalue of the k x k Lanczos
+ *               tridiagonal T_k (a lower estimate of the top of the spectrum),
+ *   bounds[1] = theta_max + |beta_{k+1} s_k|, s_k the last component of its
+ *               eigenvector (theta_max plus its Ritz residual: the usual estimate),
+ *   bounds[2] = theta_max + beta_{k+1} (safeguarded, pessimistic),
+ *   bounds[3] = theta_min, the smallest eigenvalue of T_k (an upper estimate of
+ *               the bottom of the spectrum).
+ * When the process breaks down (some beta_{j+1}, j < k, vanishes relative to
+ * the size of T_k: the Krylov space is invariant and its Ritz values need not
+ * include the extreme eigenvalues) T is cut at order j + 1 and bounds[1],
+ * bounds[2] are raised to at least, and bounds[3] lowered to at most, the
+ * Gershgorin bounds max_i (H_ii + r_i) and min_i (H_ii - r_i), r_i = sum over
+ * j != i of |H_ij|, which enclose the whole spectrum.
  * H must be FP64.  perm: device int64 [64*n_block_rows] from ttdft_bsr_build
- * (padding rows marked -1).  bound: host double[3].  Synchronises the stream.
+ * (padding rows marked -1).  bounds: host double[4].  Synchronises the stream.
  * Errors: NULL, SHAPE (k outside 1..1000), DTYPE, WORKSPACE, NONFINITE, HIP.
- */
-ttdft_status ttdft_lanczos_upper_bound(const ttdft_bsr *H, const int64_t *perm, int32_t k,
-                                       uint64_t seed, double *bound, void *work,
-                                       size_t work_bytes, void *stream);
-
-/*
- * The same k Lanczos steps, returning both ends: bounds[0..2] as bound[0..2]
- * above and bounds[3] = theta_min, the smallest eigenvalue of the Lanczos
- * tridiagonal (an upper estimate of the bottom of the spectrum; the first pass
- * of the subspace iteration takes its scaling point a0 and its cut a from it
- * and the upper estimate).  bounds: host double[4].  Synchronises the stream.
- * Workspace: ttdft_lanczos_workspace.  Errors: as ttdft_lanczos_upper_bound.
  */
 ttdft_status ttdft_lanczos_bounds(const ttdft_bsr *H, const int64_t *perm, int32_t k,
                                   uint64_t seed, double *bounds, void *work, size_t work_bytes,
@@ -412,6 +426,103 @@ ttdft_status ttdft_cheb_filter_backward(const ttdft_bsr *H, const void *X, int64
                                         int32_t ckpt_every, void *dX, int64_t lddx,
                                         void *dH_vals, const uint64_t *mask, void *work,
                                         size_t work_bytes, void *stream);
+
+/* ---------------------------------------------------------------- the subspace iteration */
+
+/*
+ * Bounds of the next pass of the subspace iteration (Sec. 3.4) from the Ritz
+ * values of this one: bounds = {a0', a', b} with a0' the smallest and a' the
+ * largest of the n values at lambda (device FP64) and b kept.  Requires
+ * a0' < a' < b.  bounds: host double[3].  Synchronises the stream.
+ * Errors: NULL, SHAPE (n < 2), BOUNDS (b not finite, or the values do not
+ * leave a0' < a' < b), NONFINITE (a non-finite value), HIP.
+ */
+ttdft_status ttdft_next_bounds(const double *lambda, int64_t n, double b, double *bounds,
+                               void *stream);
+
+/* One pass of the subspace iteration, as recorded by ttdft_chfsi_pass / _solve. */
+typedef struct {
+  int32_t pass;            /* 1-based pass number                                      */
+  int32_t m;               /* degree of this attempt                                   */
+  int32_t rank_deficient;  /* 1: the filtered block lost rank in FP64 (Cholesky
+                              breakdown); the solve repeats the pass at half the degree */
+  int32_t reserved;
+  double a0, a, b;         /* bounds the filter used                                   */
+  double max_residual;     /* largest Ritz residual norm over the lowest n_conv pairs
+                              (NaN for a rank-deficient attempt)                        */
+  double filter_ms, rr_ms, residual_ms;   /* HIP event times of the three steps       */
+} ttdft_chfsi_record;
+
+/* Bytes of workspace ttdft_chfsi_pass needs. */
+size_t ttdft_chfsi_pass_workspace(const ttdft_bsr *Hf, const ttdft_bsr *H64, int64_t n_vec,
+                                  ttdft_dtype x_dtype);
+
+/*
+ * One pass of Algorithm 1 (Sec. 3.4) followed by its convergence test:
+ *   Y = ttdft_cheb_filter(Hf, X, m, a, b, a0)   in the precision of Hf / x_dtype,
+ *   (lambda, Psi) = ttdft_rayleigh_ritz(H64, Y)  in FP64,
+ *   res = ttdft_ritz_residuals(H64, Psi, lambda),
+ *   next_bounds = ttdft_next_bounds(lambda, n_vec, b).
+ * Hf: the filter's matrix (F64 with x_dtype F64; F32, BF16 or BF16_SPLIT with
+ * x_dtype F32); H64: the same blocked matrix in FP64.  bounds: host {a0, a, b}.
+ * X: device 64*n_block_rows x n_vec of x_dtype (ldx).  lambda, res: device FP64
+ * [n_vec]; Psi: device FP64 64*n_block_rows x n_vec (ldpsi).  record (host, may
+ * be NULL) receives m, the bounds, the largest residual over the lowest n_conv
+ * pairs and the step times.  next_bounds: host double[3].  Synchronises.
+ * Errors: those of the four steps (NOT_POSDEF when the filtered block is
+ * rank-deficient in FP64; NONFINITE when it holds a NaN or Inf), NULL, SHAPE,
+ * DTYPE, BOUNDS, DEGREE, WORKSPACE.
+ */
+ttdft_status ttdft_chfsi_pass(const ttdft_bsr *Hf, const ttdft_bsr *H64, const void *X, int64_t ldx,
+                              ttdft_dtype x_dtype, int64_t n_vec, int32_t m, const double *bounds,
+                              int64_t n_conv, double *lambda, double *Psi, int64_t ldpsi,
+                              double *res, ttdft_chfsi_record *record, double *next_bounds,
+                              void *work, size_t work_bytes, void *stream);
+
+/* Bytes of workspace ttdft_chfsi_solve needs (lanczos_k = 0 when bounds are given). */
+size_t ttdft_chfsi_solve_workspace(const ttdft_bsr *Hf, const ttdft_bsr *H64, int64_t n_vec,
+                                   ttdft_dtype x_dtype, int32_t lanczos_k);
+
+/*
+ * Algorithm 1 repeated until the Ritz residual norms of the lowest n_conv
+ * pairs are at most tol (Sec. 3.4): passes of ttdft_chfsi_pass, each started
+ * from the previous pass's Ritz vectors with the bounds it returned.  The
+ * first pass uses bounds (host {a0, a, b}) when given, else k = lanczos_k
+ * Lanczos steps (ttdft_lanczos_bounds with seed): b = the safeguarded upper
+ * bound, a0 = theta_min, a = (theta_min + b) / 2.  The first pass uses degree
+ * m_first when m_first > 0, the others m.  An attempt whose filtered block is
+ * rank-deficient in FP64 (Cholesky breakdown) is repeated at half the degree
+ * (down to 1).  X (device, x_dtype F64 or F32, read only) is the start block;
+ * lambda, Psi, res receive the last pass.  history (host, history_cap records,
+ * may be NULL when history_cap = 0) receives one record per attempt;
+ * *n_records (host) the number of attempts (records beyond history_cap are
+ * dropped).  X, Psi and work must not overlap.  Synchronises.
+ * Returns TTDFT_OK once converged, TTDFT_ERR_NO_CONVERGENCE after max_passes
+ * passes without convergence (outputs hold the last pass), or the error of a step.
+ */
+ttdft_status ttdft_chfsi_solve(const ttdft_bsr *Hf, const ttdft_bsr *H64, const int64_t *perm,
+                               const void *X, int64_t ldx, ttdft_dtype x_dtype, int64_t n_vec,
+                               int32_t m, int32_t m_first, double tol, int64_t n_conv,
+                               int32_t max_passes, const double *bounds, int32_t lanczos_k,
+                               uint64_t seed, double *lambda, double *Psi, int64_t ldpsi,
+                               double *res, ttdft_chfsi_record *history, int32_t history_cap,
+                               int32_t *n_records, void *work, size_t work_bytes, void *stream);
+
+/* ---------------------------------------------------------------- finiteness check */
+
+/* Bytes of workspace ttdft_check_finite needs (a device counter). */
+size_t ttdft_check_finite_workspace(void);
+
+/*
+ * Counts the NaN and Inf entries of a rows x cols device block of dtype (F64,
+ * F32 or BF16; leading dim ld): *n_nonfinite (host).  Returns
+ * TTDFT_ERR_NONFINITE when the count is not zero (for example a filtered block
+ * that overflowed), TTDFT_OK otherwise.  Synchronises.
+ * Errors: NULL, SHAPE, DTYPE, WORKSPACE, ALIAS, NONFINITE, HIP.
+ */
+ttdft_status ttdft_check_finite(const void *A, ttdft_dtype dtype, int64_t rows, int64_t cols,
+                                int64_t ld, int64_t *n_nonfinite, void *work, size_t work_bytes,
+                                void *stream);
 
 /* ---------------------------------------------------------------- diagnostics */
 

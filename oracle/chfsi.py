@@ -153,7 +153,9 @@ def cheb_filter_adjoint(H, X, dY, m: int, a: float, b: float, a0: float,
 def orth(Y):
     """Orthonormal basis of span(Y): the thin QR factor Q with positive
     diagonal R (unique for full-rank Y), from Householder QR."""
-    Q, R = np.linalg.qr(np.asarray(Y, dtype=np.float64), mode="reduced")
+    import scipy.linalg as sla
+
+    Q, R = sla.qr(np.asarray(Y, dtype=np.float64), mode="economic", check_finite=False)
     s = np.sign(np.diag(R))
     s[s == 0] = 1.0
     return Q * s

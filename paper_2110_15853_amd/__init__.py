@@ -22,10 +22,11 @@ from .api import (  # noqa: F401
     cheb_filter_autograd,
     cheb_filter_backward,
     cholqr2,
-    lanczos_upper_bound,
     lanczos_bounds,
     ritz_residuals,
     chfsi_solve,
+    chfsi_pass,
+    check_finite,
     fermi_level,
     density_matrix,
     electron_density,

@@ -23,6 +23,14 @@ class TtdftError(RuntimeError):
         self.name = STATUS.get(status, str(status))
 
 
+class ChfsiRecord(C.Structure):
+    """ttdft_chfsi_record."""
+    _fields_ = [("pass_", C.c_int32), ("m", C.c_int32), ("rank_deficient", C.c_int32),
+                ("reserved", C.c_int32), ("a0", C.c_double), ("a", C.c_double), ("b", C.c_double),
+                ("max_residual", C.c_double), ("filter_ms", C.c_double), ("rr_ms", C.c_double),
+                ("residual_ms", C.c_double)]
+
+
 class Bsr(C.Structure):
     _fields_ = [("n_block_rows", C.c_int64), ("n_tiles", C.c_int64),
                 ("tile_rowptr", C.c_void_p), ("tile_col", C.c_void_p),
@@ -39,6 +47,7 @@ _BSRP = C.POINTER(Bsr)
 # name -> (restype, argtypes); mirrors include/ttdft.h
 SIGNATURES = {
     "ttdft_bsr_plan": (_INT, [_I32, _P, _P, _P, _P]),
+    "ttdft_bsr_build_size": (_INT, [_I32, _I32, _P, _P, _P]),
     "ttdft_bsr_build": (_INT, [_I32, _P, _P, _P, _INT, _P, _P, _P, _P, _P, _P, _P]),
     "ttdft_cheb_step": (_INT, [_BSRP, _P, _I64, _P, _I64, _P, _I64, _I64, _D, _D, _D, _INT, _P]),
     "ttdft_cheb_filter_workspace": (_SZ, [_BSRP, _I64, _INT]),
@@ -59,7 +68,6 @@ SIGNATURES = {
     "ttdft_cheb_filter_backward": (_INT, [_BSRP, _P, _I64, _P, _I64, _I64, _I32, _D, _D, _D, _INT,
                                           _I32, _P, _I64, _P, _P, _P, _SZ, _P]),
     "ttdft_lanczos_workspace": (_SZ, [_BSRP, _I32]),
-    "ttdft_lanczos_upper_bound": (_INT, [_BSRP, _P, _I32, C.c_uint64, _P, _P, _SZ, _P]),
     "ttdft_lanczos_bounds": (_INT, [_BSRP, _P, _I32, C.c_uint64, _P, _P, _SZ, _P]),
     "ttdft_ritz_residuals_workspace": (_SZ, [_BSRP, _I64]),
     "ttdft_ritz_residuals": (_INT, [_BSRP, _P, _I64, _P, _I64, _P, _P, _SZ, _P]),
@@ -68,6 +76,16 @@ SIGNATURES = {
     "ttdft_fermi_level": (_INT, [_P, _I64, C.c_double, C.c_double, _P, _P, _P, _SZ, _P]),
     "ttdft_density_matrix": (_INT, [_BSRP, _P, _I64, _P, _I64, _P, _P, _P]),
     "ttdft_electron_density": (_INT, [_P, _I64, _P, _I64, _I64, _P, _P]),
+    "ttdft_next_bounds": (_INT, [_P, _I64, _D, _P, _P]),
+    "ttdft_chfsi_pass_workspace": (_SZ, [_BSRP, _BSRP, _I64, _INT]),
+    "ttdft_chfsi_pass": (_INT, [_BSRP, _BSRP, _P, _I64, _INT, _I64, _I32, _P, _I64, _P, _P, _I64,
+                                _P, _P, _P, _P, _SZ, _P]),
+    "ttdft_chfsi_solve_workspace": (_SZ, [_BSRP, _BSRP, _I64, _INT, _I32]),
+    "ttdft_chfsi_solve": (_INT, [_BSRP, _BSRP, _P, _P, _I64, _INT, _I64, _I32, _I32, _D, _I64,
+                                 _I32, _P, _I32, C.c_uint64, _P, _P, _I64, _P, _P, _I32, _P, _P,
+                                 _SZ, _P]),
+    "ttdft_check_finite_workspace": (_SZ, []),
+    "ttdft_check_finite": (_INT, [_P, _INT, _I64, _I64, _I64, _P, _P, _SZ, _P]),
     "ttdft_status_string": (C.c_char_p, [_INT]),
     "ttdft_last_error": (C.c_char_p, []),
     "ttdft_version": (C.c_char_p, []),

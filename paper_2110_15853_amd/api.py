@@ -310,24 +310,11 @@ def chfsi_iteration(Hf: BsrMatrix, H64: BsrMatrix, X: torch.Tensor, m: int, a: f
 
 
 def updated_bounds(lam: torch.Tensor, b: float):
-    """Bounds for the next pass from the Ritz values of this one: the scaling
-    point a0 moves to the smallest Ritz value and the lower end a of the
-    unwanted interval to the largest, the upper bound b is kept."""
-    lo, hi = float(lam.min()), float(lam.max())
-    if not (lo < hi < b):
-        raise ValueError("Ritz values do not leave a0 < a < b")
-    return lo, hi
-
-
-def lanczos_upper_bound(H: BsrMatrix, k: int = 20, seed: int = 0):
-    """ttdft_lanczos_upper_bound: (theta_max, theta_max + Ritz residual,
-    theta_max + beta_{k+1}) for an FP64 H."""
-    hs = H.c_struct()
+    """ttdft_next_bounds: the scaling point a0 and the cut a of the next pass
+    (the smallest and largest Ritz value of this one; b is kept).  Returns (a0, a)."""
     out = (C.c_double * 3)()
-    w = _work(_lib.load().ttdft_lanczos_workspace(C.byref(hs), k), H.vals.device)
-    _lib.call("ttdft_lanczos_upper_bound", C.byref(hs), _ptr(H.perm), k, seed, out, _ptr(w),
-              w.numel(), _stream())
-    return float(out[0]), float(out[1]), float(out[2])
+    _lib.call("ttdft_next_bounds", _ptr(lam), lam.numel(), float(b), out, _stream())
+    return float(out[0]), float(out[1])
 
 
 def lanczos_bounds(H: BsrMatrix, k: int = 20, seed: int = 0):
@@ -356,86 +343,93 @@ def ritz_residuals(H: BsrMatrix, Psi: torch.Tensor, lam: torch.Tensor,
     return res
 
 
-def with_degree_backoff(run_pass, deg: int, on_breakdown=None):
-    """run_pass(deg) -> result; while it raises a Cholesky breakdown
-    (TTDFT_ERR_NOT_POSDEF: the filtered block is rank-deficient in FP64), call
-    on_breakdown(deg) and retry with half the degree, down to 1.  Other errors,
-    and a breakdown at degree 1, propagate.  Returns (degree used, result)."""
-    while True:
-        try:
-            return deg, run_pass(deg)
-        except _lib.TtdftError as err:
-            if err.name != "TTDFT_ERR_NOT_POSDEF" or deg == 1:
-                raise
-            if on_breakdown is not None:
-                on_breakdown(deg)
-            deg = max(1, deg // 2)
+def _record_dict(r) -> dict:
+    rec = {"pass": r.pass_, "m": r.m, "a0": r.a0, "a": r.a, "b": r.b}
+    if r.rank_deficient:
+        rec.update(max_residual=None, rank_deficient=True)
+    else:
+        rec.update(max_residual=r.max_residual, filter_ms=r.filter_ms, rr_ms=r.rr_ms,
+                   residual_ms=r.residual_ms)
+    return rec
+
+
+def _x_code(Hf: BsrMatrix) -> int:
+    return F64 if Hf.dtype == F64 else F32
+
+
+def chfsi_pass(Hf: BsrMatrix, H64: BsrMatrix, X: torch.Tensor, m: int, bounds, n_conv: int = None,
+               work: torch.Tensor = None):
+    """ttdft_chfsi_pass: one pass of Algorithm 1 (filter with Hf, FP64
+    Rayleigh-Ritz with H64) and its Ritz residuals.  bounds = (a0, a, b).
+    Returns (lambda, Psi, residuals, record dict, next bounds (a0, a, b))."""
+    n = X.shape[1]
+    n_conv = n if n_conv is None else n_conv
+    hf, h64 = Hf.c_struct(), H64.c_struct()
+    code = _code(X)
+    need = _lib.load().ttdft_chfsi_pass_workspace(C.byref(hf), C.byref(h64), n, code)
+    if work is None or work.numel() < need:
+        work = _work(need, X.device)
+    lam = torch.empty(n, dtype=torch.float64, device=X.device)
+    Psi = torch.empty((H64.rows, n), dtype=torch.float64, device=X.device)
+    res = torch.empty(n, dtype=torch.float64, device=X.device)
+    rec = _lib.ChfsiRecord()
+    nxt = (C.c_double * 3)()
+    b_in = (C.c_double * 3)(*[float(v) for v in bounds])
+    _lib.call("ttdft_chfsi_pass", C.byref(hf), C.byref(h64), _ptr(X), _ld(X), code, n, m, b_in,
+              n_conv, _ptr(lam), _ptr(Psi), _ld(Psi), _ptr(res), C.byref(rec), nxt, _ptr(work),
+              work.numel(), _stream())
+    return lam, Psi, res, _record_dict(rec), (float(nxt[0]), float(nxt[1]), float(nxt[2]))
 
 
 def chfsi_solve(Hf: BsrMatrix, H64: BsrMatrix, X0: torch.Tensor, m: int, tol: float,
                 n_conv: int = None, max_iter: int = 20, m_first: int = None, bounds=None,
-                lanczos_k: int = 30, seed: int = 0, timed: bool = False):
-    """Algorithm 1 repeated to convergence (Sec. 3.4): the filter with Hf (any
-    supported precision), FP64 Rayleigh-Ritz with H64, Ritz residual norms; the
-    next pass starts from the Ritz vectors Psi with the scaling point a0 and the
-    cut a moved to the smallest and largest Ritz values, until the residuals of
-    the lowest n_conv pairs are at most tol.  The first pass uses `bounds`
-    (a0, a, b) if given, else Lanczos estimates: b = the safeguarded upper
-    bound, a0 = theta_min, a = (theta_min + b) / 2; it may use a higher degree
-    m_first (the paper raises m for a random start).  A pass whose filtered
-    block is rank-deficient in FP64 (Rayleigh-Ritz reports a Cholesky
-    breakdown: the filter spread the block's components over more than the
-    FP64 range) is repeated with half the degree.
-    With timed=True every history entry also holds the filter, Rayleigh-Ritz
-    and residual times (ms, HIP events on the current stream).
-    Returns (lambda, Psi, residuals, history)."""
+                lanczos_k: int = 30, seed: int = 0, history_cap: int = 256):
+    """ttdft_chfsi_solve: Algorithm 1 repeated until the Ritz residual norms of
+    the lowest n_conv pairs are at most tol (Sec. 3.4), the whole loop in the
+    library.  The filter runs with Hf in its precision (FP64 iterates for an
+    FP64 Hf, FP32 otherwise; X0 is cast once), the Rayleigh-Ritz step with the
+    FP64 H64.  bounds = (a0, a, b) for the first pass, else Lanczos estimates
+    (lanczos_k steps, seed).  Returns (lambda, Psi, residuals, history) with one
+    history dict per attempt (pass, m, a0, a, b, max_residual and the step
+    times; rank-deficient attempts marked).  Without convergence in max_iter
+    passes (TTDFT_ERR_NO_CONVERGENCE) the last pass is returned; the history's
+    last max_residual shows it.  Other errors raise TtdftError."""
     n = X0.shape[1]
     n_conv = n if n_conv is None else n_conv
-    if not 1 <= n_conv <= n:
-        raise ValueError("n_conv must be in 1 .. n")
-    if bounds is None:
-        _, _, b, th_min = lanczos_bounds(H64, lanczos_k, seed)
-        a0, a = th_min, 0.5 * (th_min + b)
-    else:
-        a0, a, b = bounds
-    xdt = torch.float64 if Hf.dtype == F64 else torch.float32
+    xcode = _x_code(Hf)
+    xdt = torch.float64 if xcode == F64 else torch.float32
     X = X0 if X0.dtype == xdt else cast(X0, xdt)
-    rr_work = torch.empty(rayleigh_ritz_workspace(H64, n, xdt), dtype=torch.uint8, device=X0.device)
-    res_work = _work(_lib.load().ttdft_ritz_residuals_workspace(C.byref(H64.c_struct()), n), X0.device)
-    history = []
-    lam = Psi = res = None
-    for it in range(max_iter):
-        deg = m_first if (it == 0 and m_first) else m
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if timed else None
-        def one_pass(deg):
-            if timed:
-                ev[0].record()
-            Y = cheb_filter(Hf, X, deg, a, b, a0)
-            if timed:
-                ev[1].record()
-            return rayleigh_ritz(H64, Y, work=rr_work)
-
-        def note(deg):
-            history.append({"pass": it + 1, "m": deg, "a0": a0, "a": a, "b": b,
-                            "max_residual": None, "rank_deficient": True})
-
-        deg, (lam, Psi) = with_degree_backoff(one_pass, deg, note)
-        if timed:
-            ev[2].record()
-        res = ritz_residuals(H64, Psi, lam, work=res_work)
-        if timed:
-            ev[3].record()
-        worst = float(res[:n_conv].max())
-        rec = {"pass": it + 1, "m": deg, "a0": a0, "a": a, "b": b, "max_residual": worst}
-        if timed:
-            rec.update(filter_ms=ev[0].elapsed_time(ev[1]), rr_ms=ev[1].elapsed_time(ev[2]),
-                       residual_ms=ev[2].elapsed_time(ev[3]))
-        history.append(rec)
-        if worst <= tol:
-            break
-        a0, a = updated_bounds(lam, b)
-        X = Psi if xdt == torch.float64 else cast(Psi, xdt)
+    hf, h64 = Hf.c_struct(), H64.c_struct()
+    k = 0 if bounds is not None else lanczos_k
+    need = _lib.load().ttdft_chfsi_solve_workspace(C.byref(hf), C.byref(h64), n, xcode, k)
+    work = _work(need, X.device)
+    lam = torch.empty(n, dtype=torch.float64, device=X.device)
+    Psi = torch.empty((H64.rows, n), dtype=torch.float64, device=X.device)
+    res = torch.empty(n, dtype=torch.float64, device=X.device)
+    hist = (_lib.ChfsiRecord * history_cap)()
+    n_rec = C.c_int32(0)
+    b_in = (C.c_double * 3)(*[float(v) for v in bounds]) if bounds is not None else None
+    lib = _lib.load()
+    st = lib.ttdft_chfsi_solve(C.byref(hf), C.byref(h64), _ptr(H64.perm), _ptr(X), _ld(X), xcode, n,
+                               m, m_first or 0, float(tol), n_conv, max_iter, b_in, lanczos_k, seed,
+                               _ptr(lam), _ptr(Psi), _ld(Psi), _ptr(res), hist, history_cap,
+                               C.byref(n_rec), _ptr(work), work.numel(), _stream())
+    if st not in (0, 9):            # 9: TTDFT_ERR_NO_CONVERGENCE, outputs hold the last pass
+        raise _lib.TtdftError(st, lib.ttdft_last_error().decode())
+    history = [_record_dict(hist[i]) for i in range(min(n_rec.value, history_cap))]
     return lam, Psi, res, history
+
+
+def check_finite(A: torch.Tensor) -> int:
+    """ttdft_check_finite: the number of NaN / Inf entries of a 2-D block
+    (0 when all are finite)."""
+    cnt = C.c_int64(0)
+    w = _work(_lib.load().ttdft_check_finite_workspace(), A.device)
+    st = _lib.load().ttdft_check_finite(_ptr(A), _code(A), A.shape[0], A.shape[1], _ld(A),
+                                        C.byref(cnt), _ptr(w), w.numel(), _stream())
+    if st not in (0, 10):
+        raise _lib.TtdftError(st, _lib.load().ttdft_last_error().decode())
+    return int(cnt.value)
 
 
 KT_500K_HARTREE = 500.0 * 3.166811563e-6   # k_B T at the paper's smearing temperature, in Hartree

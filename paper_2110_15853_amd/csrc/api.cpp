@@ -230,6 +230,14 @@ ttdft_status ttdft_bsr_plan(int32_t r, const int64_t *rowptr, const int32_t *col
   return ok();
 }
 
+ttdft_status ttdft_bsr_build_size(int32_t r, int32_t blk, const int64_t *rowptr, const int32_t *col,
+                                  int64_t *n_tiles_out) {
+  if (!n_tiles_out) return fail(TTDFT_ERR_NULL, "n_tiles_out is NULL");
+  if (blk != 4) return fail(TTDFT_ERR_SHAPE, "tile extent blk = %d: only 4 (64-row tiles) is built", blk);
+  int64_t nbr = 0;
+  return ttdft_bsr_plan(r, rowptr, col, &nbr, n_tiles_out);
+}
+
 ttdft_status ttdft_bsr_build(int32_t r, const int64_t *rowptr, const int32_t *col,
                              const double *val, ttdft_dtype dtype, int32_t *tile_rowptr,
                              int32_t *tile_col, void *vals, int64_t *perm, int64_t *entry_slot,
@@ -295,6 +303,8 @@ ttdft_status ttdft_cheb_step(const ttdft_bsr *H, const void *Yk, int64_t ldk, co
   if (n_vec < 1) return fail(TTDFT_ERR_SHAPE, "n_vec = %lld < 1", (long long)n_vec);
   if (ldk < n_vec || ldo < n_vec || (Yprev && ldp < n_vec))
     return fail(TTDFT_ERR_SHAPE, "leading dimension smaller than n_vec");
+  if (!step_ld_ok(ldk, dtype_size(x_dtype)))
+    return fail(TTDFT_ERR_SHAPE, "ldk = %lld too large for 32-bit panel offsets", (long long)ldk);
   if (!std::isfinite(alpha) || !std::isfinite(c) || !std::isfinite(beta))
     return fail(TTDFT_ERR_NONFINITE, "alpha, c and beta must be finite");
   const int64_t rows = H->n_block_rows * 64;
@@ -327,6 +337,8 @@ ttdft_status ttdft_cheb_filter(const ttdft_bsr *H, const void *X, int64_t ldx, v
   if (!X || !Y) return fail(TTDFT_ERR_NULL, "X or Y is NULL");
   if (n_vec < 1) return fail(TTDFT_ERR_SHAPE, "n_vec = %lld < 1", (long long)n_vec);
   if (ldx < n_vec || ldy < n_vec) return fail(TTDFT_ERR_SHAPE, "leading dimension smaller than n_vec");
+  if (!step_ld_ok(ldx, dtype_size(x_dtype)) || !step_ld_ok(ldy, dtype_size(x_dtype)))
+    return fail(TTDFT_ERR_SHAPE, "leading dimension too large for 32-bit panel offsets");
   if (!(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0)) || !(a0 < a && a < b))
     return fail(TTDFT_ERR_BOUNDS, "bounds must be finite with a0 < a < b (got a0=%g a=%g b=%g)", a0, a, b);
   if (m < 1) return fail(TTDFT_ERR_DEGREE, "degree m = %d < 1", m);
@@ -358,6 +370,35 @@ ttdft_status ttdft_cheb_filter(const ttdft_bsr *H, const void *X, int64_t ldx, v
                                       alpha[k], c, beta[k], x_dtype, s);
     if (err != hipSuccess) return hip_status(err, "cheb_filter step");
   }
+  return ok();
+}
+
+size_t ttdft_check_finite_workspace(void) { return 16; }
+
+ttdft_status ttdft_check_finite(const void *A, ttdft_dtype dtype, int64_t rows, int64_t cols,
+                                int64_t ld, int64_t *n_nonfinite, void *work, size_t work_bytes,
+                                void *stream) {
+  if (!valid_dtype(dtype)) return fail(TTDFT_ERR_DTYPE, "unknown dtype");
+  if (!n_nonfinite) return fail(TTDFT_ERR_NULL, "n_nonfinite is NULL");
+  if (rows < 0 || cols < 0 || ld < cols) return fail(TTDFT_ERR_SHAPE, "bad block shape");
+  if (rows > 0 && cols > 0 && !A) return fail(TTDFT_ERR_NULL, "A is NULL");
+  if (!work || work_bytes < 16) return fail(TTDFT_ERR_WORKSPACE, "workspace of 16 bytes needed");
+  if (rows == 0 || cols == 0) {
+    *n_nonfinite = 0;
+    return ok();
+  }
+  if (overlap(span_of(A, rows, ld, cols, dtype_size(dtype)), span_bytes(work, 16)))
+    return fail(TTDFT_ERR_ALIAS, "workspace overlaps the block");
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long *cnt = (unsigned long long *)work;
+  hipError_t e = launch_clear_ints((int *)work, 2, s);
+  if (e == hipSuccess) e = launch_count_nonfinite(A, dtype, ld, rows, cols, cnt, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  unsigned long long h = 0;
+  if (e == hipSuccess) e = hipMemcpy(&h, cnt, sizeof h, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_status(e, "check_finite");
+  *n_nonfinite = (int64_t)h;
+  if (h) return fail(TTDFT_ERR_NONFINITE, "%llu non-finite entries", h);
   return ok();
 }
 

@@ -99,6 +99,9 @@ ttdft_status ttdft_cheb_filter_backward(const ttdft_bsr *H, const void *X, int64
   if (!X || !dY || !dX || !dH_vals) return failf(TTDFT_ERR_NULL, "X, dY, dX or dH_vals is NULL");
   if (n_vec < 1 || ldx < n_vec || lddy < n_vec || lddx < n_vec)
     return failf(TTDFT_ERR_SHAPE, "leading dimension smaller than n_vec");
+  if (!step_ld_ok(ldx, dtype_size(x_dtype)) || !step_ld_ok(lddy, dtype_size(x_dtype)) ||
+      !step_ld_ok(lddx, dtype_size(x_dtype)))
+    return failf(TTDFT_ERR_SHAPE, "leading dimension too large for 32-bit panel offsets");
   if (!(std::isfinite(a) && std::isfinite(b) && std::isfinite(a0)) || !(a0 < a && a < b))
     return failf(TTDFT_ERR_BOUNDS, "bounds must be finite with a0 < a < b");
   if (m < 1) return failf(TTDFT_ERR_DEGREE, "degree m = %d < 1", m);

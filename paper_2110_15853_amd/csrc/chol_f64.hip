@@ -49,6 +49,7 @@ __global__ void gram_scale_diag_kernel(const double *G, int64_t n, int64_t np, d
       const double g = G[i * np + i];
       if (!(g > 0.0) || !isfinite(g)) {
         atomicCAS(info, 0, (int)(i + 1));
+        if (!isfinite(g)) atomicOr(info + 1, 1);   // a NaN or Inf in the block
         d[i] = 1.0;
       } else {
         d[i] = sqrt(g);

@@ -115,4 +115,41 @@ hipError_t launch_split_bf16(const double *src, int64_t n_tiles, void *dst, hipS
   return hipGetLastError();
 }
 
+namespace {
+template <typename T> __device__ inline bool is_finite_elt(T v) { return isfinite(v); }
+template <> __device__ inline bool is_finite_elt<__bf16>(__bf16 v) { return isfinite((float)v); }
+
+// *count += number of non-finite entries of a rows x cols block (grid-stride;
+// one atomic add of a wave's count per wave and pass; the total is exact)
+template <typename T>
+__global__ __launch_bounds__(256) void count_nonfinite_kernel(const T *__restrict__ A, int64_t ld,
+                                                              int64_t rows, int64_t cols,
+                                                              unsigned long long *count) {
+  const int64_t chunks = (cols + 255) / 256;
+  unsigned long long bad = 0;
+  for (int64_t w = blockIdx.x; w < rows * chunks; w += gridDim.x) {
+    const int64_t r = w / chunks, c = (w % chunks) * 256 + threadIdx.x;
+    if (c < cols && !is_finite_elt<T>(A[r * ld + c])) ++bad;
+  }
+  for (int o = 32; o > 0; o >>= 1) bad += __shfl_down(bad, o, 64);
+  if ((threadIdx.x & 63) == 0 && bad) atomicAdd(count, bad);
+}
+}  // namespace
+
+hipError_t launch_count_nonfinite(const void *A, ttdft_dtype dt, int64_t ld, int64_t rows,
+                                  int64_t cols, unsigned long long *count, hipStream_t s) {
+  if (rows == 0 || cols == 0) return hipSuccess;
+  const unsigned g = grid_for(rows * ((cols + 255) / 256));
+  if (dt == TTDFT_F64)
+    hipLaunchKernelGGL(count_nonfinite_kernel<double>, dim3(g), dim3(256), 0, s, (const double *)A, ld,
+                       rows, cols, count);
+  else if (dt == TTDFT_F32)
+    hipLaunchKernelGGL(count_nonfinite_kernel<float>, dim3(g), dim3(256), 0, s, (const float *)A, ld,
+                       rows, cols, count);
+  else
+    hipLaunchKernelGGL(count_nonfinite_kernel<__bf16>, dim3(g), dim3(256), 0, s, (const __bf16 *)A, ld,
+                       rows, cols, count);
+  return hipGetLastError();
+}
+
 }  // namespace ttdft

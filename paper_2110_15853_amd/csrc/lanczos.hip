@@ -8,7 +8,16 @@
 // the safeguarded bound theta_max + beta_{k+1}.  The product H v uses
 // the fused step kernel with alpha = 1, c = 0, beta = 0 on one vector; the
 // reductions run in a single work-group in a fixed order (deterministic).
+//
+// Breakdown: when some beta_{j+1} vanishes (to rounding, relative to the size of
+// T_k) the Krylov space is an invariant subspace of H after j steps.  T_j then
+// holds exact eigenvalues of H, but not necessarily its extreme ones, and the
+// steps after it would only append spurious zero rows.  The bounds are then
+// taken from T_j and widened to the Gershgorin interval of H (every eigenvalue
+// lies in some row's disc [H_ii - r_i, H_ii + r_i], r_i = sum_{j != i} |H_ij|).
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "ttdft_internal.h"
 
@@ -57,7 +66,8 @@ __global__ void lz_update_kernel(double *w, const double *v, const double *vprev
     w[i] -= al * v[i] + (vprev ? be * vprev[i] : 0.0);
 }
 
-// beta = |w|; v_next = w / beta (a zero w restarts from a fresh random vector)
+// beta = |w|; v_next = w / beta (v_next = 0 when w = 0: a breakdown, which the
+// host detects from beta and handles by truncating T_k)
 __global__ __launch_bounds__(1024) void lz_normalize_kernel(const double *w, double *v_next,
                                                             int64_t rows, double *beta) {
   __shared__ double red[16];
@@ -129,18 +139,82 @@ __global__ void lz_bound_kernel(const double *alpha, const double *beta, int k, 
   out[3] = lo1;   // lower end of its bracket
 }
 
+// Gershgorin discs of the real rows of block row B (one work-group of 64
+// threads, thread i = local row i): lo[B] = min_i (H_ii - r_i), hi[B] =
+// max_i (H_ii + r_i) over rows with perm >= 0 (padding rows are skipped; a
+// block row of padding only writes +inf / -inf).  Tile values are in fragment
+// order: entry (i, j) of tile t at 64*(4*(j/4) + i/16) + 16*(j%4) + i%16.
+__global__ __launch_bounds__(64) void gershgorin_kernel(const int32_t *rowptr, const int32_t *tcol,
+                                                        const double *vals, const int64_t *perm,
+                                                        double *lo, double *hi) {
+  const int64_t B = blockIdx.x;
+  const int i = threadIdx.x;
+  double diag = 0.0, rad = 0.0;
+  for (int t = rowptr[B]; t < rowptr[B + 1]; ++t) {
+    const double *tile = vals + (int64_t)t * 4096;
+    const bool dtile = tcol[t] == B;
+    for (int j = 0; j < 64; ++j) {
+      const double v = tile[64 * (4 * (j >> 2) + (i >> 4)) + 16 * (j & 3) + (i & 15)];
+      if (dtile && j == i) diag = v;
+      else rad += fabs(v);
+    }
+  }
+  const bool real = perm[B * 64 + i] >= 0;
+  double l = real ? diag - rad : INFINITY, h = real ? diag + rad : -INFINITY;
+  for (int o = 32; o > 0; o >>= 1) {
+    l = fmin(l, __shfl_down(l, o, 64));
+    h = fmax(h, __shfl_down(h, o, 64));
+  }
+  if (i == 0) {
+    lo[B] = l;
+    hi[B] = h;
+  }
+}
+
+// out[0] = min(lo), out[1] = max(hi) over nb entries (one work-group)
+__global__ __launch_bounds__(1024) void minmax_kernel(const double *lo, const double *hi, int64_t nb,
+                                                      double *out) {
+  __shared__ double sl[16], sh[16];
+  double l = INFINITY, h = -INFINITY;
+  for (int64_t b = threadIdx.x; b < nb; b += 1024) {
+    l = fmin(l, lo[b]);
+    h = fmax(h, hi[b]);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    l = fmin(l, __shfl_down(l, o, 64));
+    h = fmax(h, __shfl_down(h, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sl[threadIdx.x >> 6] = l;
+    sh[threadIdx.x >> 6] = h;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 16; ++w) {
+      l = fmin(l, sl[w]);
+      h = fmax(h, sh[w]);
+    }
+    l = fmin(l, sl[0]);
+    h = fmax(h, sh[0]);
+    out[0] = l;
+    out[1] = h;
+  }
+}
+
 }  // namespace
 
 size_t lanczos_work_bytes(int64_t rows, int k) {
-  return (size_t)(3 * rows + 2 * (k + 2) + 4) * sizeof(double);
+  return (size_t)(3 * rows + 2 * (k + 2) + 4 + 2 * (rows / 64) + 2) * sizeof(double);
 }
 
-// work: 3 vectors + alpha[k+1] + beta[k+2] + out[4]
+// work: 3 vectors + alpha[k+1] + beta[k+2] + out[4] + Gershgorin lo/hi per block row + 2
 hipError_t run_lanczos_bound(const ttdft_bsr &H, const int64_t *perm, int k, uint64_t seed,
-                             void *work, hipStream_t s, double host_out[4]) {
+                             void *work, hipStream_t s, double host_out[4], int *breakdown) {
   const int64_t rows = H.n_block_rows * 64;
   double *v0 = (double *)work, *v1 = v0 + rows, *w = v1 + rows;
   double *alpha = w + rows, *beta = alpha + (k + 1), *out = beta + (k + 2);
+  double *glo = out + 4, *ghi = glo + H.n_block_rows, *gout = ghi + H.n_block_rows;
+  *breakdown = 0;
   const unsigned g = (unsigned)std::min<int64_t>((rows + 255) / 256, 4096);
   hipLaunchKernelGGL(lz_start_kernel, dim3(g), dim3(256), 0, s, w, rows, perm, seed);
   hipLaunchKernelGGL(lz_normalize_kernel, dim3(1), dim3(1024), 0, s, w, v0, rows, beta);
@@ -157,11 +231,40 @@ hipError_t run_lanczos_bound(const ttdft_bsr &H, const int64_t *perm, int k, uin
     vprev = vcur;
     vcur = target;
   }
-  hipLaunchKernelGGL(lz_bound_kernel, dim3(1), dim3(64), 0, s, alpha, beta, k, out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  // breakdown test on the host: the first beta_{j+1}, j < k, that vanishes
+  // relative to the size of T_k ends the usable tridiagonal at order j + 1
+  std::vector<double> ha(k), hb(k + 1);
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-  return hipMemcpy(host_out, out, 4 * sizeof(double), hipMemcpyDeviceToHost);
+  if ((e = hipMemcpy(ha.data(), alpha, k * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess) return e;
+  if ((e = hipMemcpy(hb.data(), beta, (k + 1) * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess) return e;
+  double scale = 0.0;
+  for (int j = 0; j < k; ++j) scale = std::max(scale, std::fabs(ha[j]) + std::fabs(hb[j + 1]));
+  int k_eff = k;
+  for (int j = 0; j + 1 < k; ++j)
+    if (!(std::fabs(hb[j + 1]) > 1e-12 * scale)) {
+      k_eff = j + 1;
+      break;
+    }
+  hipLaunchKernelGGL(lz_bound_kernel, dim3(1), dim3(64), 0, s, alpha, beta, k_eff, out);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  if ((e = hipMemcpy(host_out, out, 4 * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess) return e;
+  if (k_eff < k || !(std::fabs(hb[k]) > 1e-12 * scale)) {
+    *breakdown = 1;
+    hipLaunchKernelGGL(gershgorin_kernel, dim3((unsigned)H.n_block_rows), dim3(64), 0, s,
+                       H.tile_rowptr, H.tile_col, (const double *)H.vals, perm, glo, ghi);
+    hipLaunchKernelGGL(minmax_kernel, dim3(1), dim3(1024), 0, s, glo, ghi, H.n_block_rows, gout);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    double g[2];
+    if ((e = hipMemcpy(g, gout, sizeof g, hipMemcpyDeviceToHost)) != hipSuccess) return e;
+    host_out[1] = std::max(host_out[1], g[1]);
+    host_out[2] = std::max(host_out[2], g[1]);
+    host_out[3] = std::min(host_out[3], g[0]);
+  }
+  return hipSuccess;
 }
 
 }  // namespace ttdft

@@ -213,12 +213,15 @@ RrLayout rr_layout(int64_t rows, int64_t n) {
   return L;
 }
 
-// 0 when the enqueued passes succeeded, else the breakdown column (1-based)
-int qr_breakdown(char *work, const QrLayout &L, hipStream_t s, hipError_t *e) {
+// 0 when the enqueued passes succeeded, else the breakdown column (1-based);
+// *nonfinite is set when a Gram diagonal entry was NaN or Inf (a non-finite block)
+int qr_breakdown(char *work, const QrLayout &L, hipStream_t s, hipError_t *e, bool *nonfinite) {
+  *nonfinite = false;
   *e = hipStreamSynchronize(s);
   if (*e != hipSuccess) return 0;
   int info[2] = {0, 0};
   *e = hipMemcpy(info, work + L.info, sizeof info, hipMemcpyDeviceToHost);
+  *nonfinite = info[1] != 0;
   return info[0];
 }
 
@@ -228,14 +231,16 @@ ttdft_status orthonormalise(const void *Y, int64_t ldy, ttdft_dtype ydt, int64_t
                             bool y_intact_after) {
   hipError_t e = cholqr2_enqueue(Y, ldy, ydt, rows, n, Q, ldq, work, L, s);
   if (e != hipSuccess) return hip_fail(e, "cholqr2 launch");
-  int col = qr_breakdown(work, L, s, &e);
+  bool nonfinite;
+  int col = qr_breakdown(work, L, s, &e, &nonfinite);
   if (e != hipSuccess) return hip_fail(e, "cholqr2");
+  if (nonfinite) return failf(TTDFT_ERR_NONFINITE, "the block holds a NaN or Inf");
   if (col == 0) return TTDFT_OK;
   if (!y_intact_after)
     return failf(TTDFT_ERR_NOT_POSDEF, "Cholesky breakdown at column %d (Q aliases Y: no retry)", col);
   e = shifted_cholqr3_enqueue(Y, ldy, ydt, rows, n, Q, ldq, work, L, s);
   if (e != hipSuccess) return hip_fail(e, "shifted cholqr3 launch");
-  col = qr_breakdown(work, L, s, &e);
+  col = qr_breakdown(work, L, s, &e, &nonfinite);
   if (e != hipSuccess) return hip_fail(e, "shifted cholqr3");
   if (col) return failf(TTDFT_ERR_NOT_POSDEF, "Cholesky breakdown at column %d: block rank-deficient in FP64", col);
   return TTDFT_OK;
@@ -282,6 +287,8 @@ ttdft_status ttdft_project(const ttdft_bsr *H, const double *Q, int64_t ldq, int
   if (st != TTDFT_OK) return st;
   if (!Q || !A) return failf(TTDFT_ERR_NULL, "Q or A is NULL");
   if (n_vec < 1 || ldq < n_vec || lda < n_vec) return failf(TTDFT_ERR_SHAPE, "bad shape");
+  if (!step_ld_ok(ldq, 8) || !step_ld_ok(n_vec, 8))
+    return failf(TTDFT_ERR_SHAPE, "leading dimension too large for 32-bit panel offsets");
   const int64_t rows = H->n_block_rows * 64;
   const ProjLayout L = proj_layout(rows, n_vec);
   if (!work || work_bytes < L.total) return failf(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", L.total);
@@ -341,6 +348,7 @@ ttdft_status ttdft_rayleigh_ritz(const ttdft_bsr *H, const void *Y, int64_t ldy,
   if (!Y || !lambda || !Psi) return failf(TTDFT_ERR_NULL, "Y, lambda or Psi is NULL");
   const int64_t rows = H->n_block_rows * 64;
   if (n_vec < 1 || n_vec > rows || ldy < n_vec || ldpsi < n_vec) return failf(TTDFT_ERR_SHAPE, "bad shape");
+  if (!step_ld_ok(n_vec, 8)) return failf(TTDFT_ERR_SHAPE, "n_vec too large for 32-bit panel offsets");
   const RrLayout L = rr_layout(rows, n_vec);
   if (!work || work_bytes < L.total) return failf(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", L.total);
   const size_t elt = y_dtype == TTDFT_F64 ? 8 : y_dtype == TTDFT_F32 ? 4 : 2;
@@ -360,13 +368,15 @@ ttdft_status ttdft_rayleigh_ritz(const ttdft_bsr *H, const void *Y, int64_t ldy,
   bool implicit = true;
   hipError_t e = cholqr2_implicit_enqueue(Y, ldy, y_dtype, rows, n, XF, n, w + L.qr_off, L.qr, s);
   if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: cholqr2 launch");
-  int col = qr_breakdown(w + L.qr_off, L.qr, s, &e);
+  bool nonfinite;
+  int col = qr_breakdown(w + L.qr_off, L.qr, s, &e, &nonfinite);
   if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: cholqr2");
+  if (nonfinite) return failf(TTDFT_ERR_NONFINITE, "the filtered block holds a NaN or Inf");
   if (col) {
     implicit = false;
     e = shifted_cholqr3_enqueue(Y, ldy, y_dtype, rows, n, XF, n, w + L.qr_off, L.qr, s);
     if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: shifted cholqr3 launch");
-    col = qr_breakdown(w + L.qr_off, L.qr, s, &e);
+    col = qr_breakdown(w + L.qr_off, L.qr, s, &e, &nonfinite);
     if (e != hipSuccess) return hip_fail(e, "rayleigh_ritz: shifted cholqr3");
     if (col) return failf(TTDFT_ERR_NOT_POSDEF, "Cholesky breakdown at column %d: block rank-deficient in FP64", col);
   } else {
@@ -413,24 +423,6 @@ size_t ttdft_lanczos_workspace(const ttdft_bsr *H, int32_t k) {
   return lanczos_work_bytes(H->n_block_rows * 64, k);
 }
 
-ttdft_status ttdft_lanczos_upper_bound(const ttdft_bsr *H, const int64_t *perm, int32_t k,
-                                       uint64_t seed, double *bound, void *work,
-                                       size_t work_bytes, void *stream) {
-  ttdft_status st = check_h64(H);
-  if (st != TTDFT_OK) return st;
-  if (!perm || !bound) return failf(TTDFT_ERR_NULL, "perm or bound is NULL");
-  if (k < 1 || k > 1000) return failf(TTDFT_ERR_SHAPE, "k = %d outside 1 .. 1000", k);
-  const size_t need = lanczos_work_bytes(H->n_block_rows * 64, k);
-  if (!work || work_bytes < need) return failf(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", need);
-  double out[4];
-  hipError_t e = run_lanczos_bound(*H, perm, k, seed, work, (hipStream_t)stream, out);
-  if (e != hipSuccess) return hip_fail(e, "lanczos");
-  if (!std::isfinite(out[0]) || !std::isfinite(out[1]) || !std::isfinite(out[2]))
-    return failf(TTDFT_ERR_NONFINITE, "non-finite Lanczos estimate");
-  for (int i = 0; i < 3; ++i) bound[i] = out[i];
-  return api_ok();
-}
-
 ttdft_status ttdft_lanczos_bounds(const ttdft_bsr *H, const int64_t *perm, int32_t k,
                                   uint64_t seed, double *bounds, void *work, size_t work_bytes,
                                   void *stream) {
@@ -441,7 +433,8 @@ ttdft_status ttdft_lanczos_bounds(const ttdft_bsr *H, const int64_t *perm, int32
   const size_t need = lanczos_work_bytes(H->n_block_rows * 64, k);
   if (!work || work_bytes < need) return failf(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", need);
   double out[4];
-  hipError_t e = run_lanczos_bound(*H, perm, k, seed, work, (hipStream_t)stream, out);
+  int breakdown = 0;
+  hipError_t e = run_lanczos_bound(*H, perm, k, seed, work, (hipStream_t)stream, out, &breakdown);
   if (e != hipSuccess) return hip_fail(e, "lanczos");
   for (int i = 0; i < 4; ++i)
     if (!std::isfinite(out[i])) return failf(TTDFT_ERR_NONFINITE, "non-finite Lanczos estimate");
@@ -461,6 +454,7 @@ ttdft_status ttdft_ritz_residuals(const ttdft_bsr *H, const double *Psi, int64_t
   if (st != TTDFT_OK) return st;
   if (!Psi || !lambda || !res) return failf(TTDFT_ERR_NULL, "Psi, lambda or res is NULL");
   if (n_vec < 1 || ldp < n_vec) return failf(TTDFT_ERR_SHAPE, "bad shape");
+  if (!step_ld_ok(ldp, 8)) return failf(TTDFT_ERR_SHAPE, "leading dimension too large for 32-bit panel offsets");
   const int64_t rows = H->n_block_rows * 64;
   const size_t need = residual_work_bytes(rows, n_vec);
   if (!work || work_bytes < need) return failf(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", need);

@@ -17,6 +17,10 @@ inline size_t tile_value_bytes(ttdft_dtype t) { return t == TTDFT_BF16_SPLIT ? 4
 constexpr int kTile = 64;                    // rows per lattice block (4x4x4)
 constexpr int64_t kTileElems = 64 * 64;
 
+// The step kernel addresses a 64-row panel of a dense block with 32-bit byte
+// offsets: 64 * ld * elt must fit in an int32.
+inline bool step_ld_ok(int64_t ld, size_t elt) { return ld >= 0 && 64 * ld * (int64_t)elt <= 0x7fffffffLL; }
+
 // ---- coefficient schedule of the scaled recurrence (Algorithm 1, Sec. 3.4):
 // step k (k = 0 .. m-1) forms Y_{k+1} = alpha[k] (H - cI) Y_k - beta[k] Y_{k-1},
 // beta[0] = 0.  alpha and beta hold m entries.
@@ -32,6 +36,9 @@ hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, con
 hipError_t launch_cast(const void *src, ttdft_dtype st, int64_t lds, void *dst, ttdft_dtype dt,
                        int64_t ldd, int64_t rows, int64_t cols, hipStream_t s);
 hipError_t launch_split_bf16(const double *src, int64_t n_tiles, void *dst, hipStream_t s);
+// *count += number of NaN / Inf entries of a rows x cols block (count: device, cleared by the caller)
+hipError_t launch_count_nonfinite(const void *A, ttdft_dtype dt, int64_t ld, int64_t rows,
+                                  int64_t cols, unsigned long long *count, hipStream_t s);
 hipError_t launch_gather_rows(const void *src, int64_t lds, void *dst, int64_t ldd,
                               int64_t rows_dst, int64_t cols, const int64_t *perm, size_t elt,
                               hipStream_t s);
@@ -112,7 +119,9 @@ hipError_t run_ritz_residuals(const ttdft_bsr &H, const double *Psi, int64_t ldp
                               const double *lambda, int64_t n, double *res, void *work,
                               hipStream_t s);
 size_t lanczos_work_bytes(int64_t rows, int k);
+// host_out: theta_max, estimate, safeguarded bound, theta_min; *breakdown set when the
+// Lanczos process found an invariant subspace (bounds then widened to Gershgorin's)
 hipError_t run_lanczos_bound(const ttdft_bsr &H, const int64_t *perm, int k, uint64_t seed,
-                             void *work, hipStream_t s, double host_out[4]);
+                             void *work, hipStream_t s, double host_out[4], int *breakdown);
 
 }  // namespace ttdft

@@ -233,17 +233,6 @@ def test_backward_workspace_plan(lib_built):
     assert ws(16, 4) < ws(16, 0)
 
 
-def test_lanczos_validation(lib_built):
-    L = _lib()
-    lib = L.load()
-    H64, H32 = _fake_bsr(), _fake_bsr(dtype=1)
-    out = (C.c_double * 3)()
-    assert L.STATUS[lib.ttdft_lanczos_upper_bound(C.byref(H32), FAKE, 10, 0, out, FAKE, 1 << 30, None)] == "TTDFT_ERR_DTYPE"
-    assert L.STATUS[lib.ttdft_lanczos_upper_bound(C.byref(H64), FAKE, 0, 0, out, FAKE, 1 << 30, None)] == "TTDFT_ERR_SHAPE"
-    assert L.STATUS[lib.ttdft_lanczos_upper_bound(C.byref(H64), None, 10, 0, out, FAKE, 1 << 30, None)] == "TTDFT_ERR_NULL"
-    assert L.STATUS[lib.ttdft_lanczos_upper_bound(C.byref(H64), FAKE, 10, 0, out, FAKE, 8, None)] == "TTDFT_ERR_WORKSPACE"
-
-
 def test_lanczos_bounds_and_residuals_validation(lib_built):
     L = _lib()
     lib = L.load()
@@ -344,3 +333,158 @@ def test_split_and_step_validation(lib_built):
     H = _fake_bsr(dtype=3)
     assert L.STATUS[_filter(H=H, dt=2)] == "TTDFT_ERR_DTYPE"
     assert L.STATUS[_filter(H=H, dt=0)] == "TTDFT_ERR_DTYPE"
+
+
+def _np(a):
+    return C.c_void_p(a.ctypes.data)
+
+
+def test_bsr_build_size_matches_plan(lib_built):
+    L = _lib()
+    lib = L.load()
+    ip, ix, d, N = workload.lattice_hamiltonian(6, 2, 0)
+    ip = np.ascontiguousarray(ip, np.int64)
+    ix = np.ascontiguousarray(ix, np.int32)
+    nbr, nt, nt2 = C.c_int64(), C.c_int64(), C.c_int64()
+    assert lib.ttdft_bsr_plan(6, _np(ip), _np(ix), C.byref(nbr), C.byref(nt)) == 0
+    assert lib.ttdft_bsr_build_size(6, 4, _np(ip), _np(ix), C.byref(nt2)) == 0
+    assert nt2.value == nt.value and nbr.value == 8
+    assert L.STATUS[lib.ttdft_bsr_build_size(6, 3, _np(ip), _np(ix), C.byref(nt2))] == "TTDFT_ERR_SHAPE"
+    assert L.STATUS[lib.ttdft_bsr_build_size(6, 4, _np(ip), _np(ix), None)] == "TTDFT_ERR_NULL"
+    assert L.STATUS[lib.ttdft_bsr_build_size(6, 4, None, _np(ix), C.byref(nt2))] == "TTDFT_ERR_NULL"
+
+
+def test_leading_dimension_limit_for_panel_offsets(lib_built):
+    # the step kernel addresses a 64-row panel with 32-bit byte offsets:
+    # 64 * ld * element size must stay below 2^31
+    L = _lib()
+    lib = L.load()
+    big64, big32 = 1 << 22, 1 << 23
+    assert L.STATUS[_filter(ldx=big64)] == "TTDFT_ERR_SHAPE"
+    assert L.STATUS[_filter(ldy=big64)] == "TTDFT_ERR_SHAPE"
+    assert L.STATUS[_filter(H=_fake_bsr(dtype=1), dt=1, ldx=big32)] == "TTDFT_ERR_SHAPE"
+    H = _fake_bsr()
+    assert L.STATUS[lib.ttdft_cheb_step(C.byref(H), FAKE, big64, None, 0, FAKE * 1000, 16, 16, 1.0,
+                                        0.0, 0.0, 0, None)] == "TTDFT_ERR_SHAPE"
+    need = lib.ttdft_cheb_filter_backward_workspace(C.byref(H), 16, 4, 0, 0)
+    assert L.STATUS[lib.ttdft_cheb_filter_backward(
+        C.byref(H), FAKE, 16, FAKE * 1000, 16, 16, 4, 2.0, 12.5, -3.0, 0, 0, FAKE * 2000, big64,
+        FAKE * 3000, None, FAKE * 100000, need, None)] == "TTDFT_ERR_SHAPE"
+    W = FAKE + (1 << 36)
+    rneed = lib.ttdft_ritz_residuals_workspace(C.byref(H), 16)
+    assert L.STATUS[lib.ttdft_ritz_residuals(C.byref(H), FAKE, big64, FAKE + (1 << 34), 16,
+                                             FAKE + (1 << 35), W, rneed, None)] == "TTDFT_ERR_SHAPE"
+    pneed = lib.ttdft_project_workspace(C.byref(H), 16)
+    assert L.STATUS[lib.ttdft_project(C.byref(H), FAKE, big64, 16, FAKE + (1 << 34), 16, W, pneed,
+                                      None)] == "TTDFT_ERR_SHAPE"
+
+
+def test_next_bounds_validation(lib_built):
+    L = _lib()
+    lib = L.load()
+    out = (C.c_double * 3)()
+    assert L.STATUS[lib.ttdft_next_bounds(None, 8, 12.5, out, None)] == "TTDFT_ERR_NULL"
+    assert L.STATUS[lib.ttdft_next_bounds(FAKE, 8, 12.5, None, None)] == "TTDFT_ERR_NULL"
+    assert L.STATUS[lib.ttdft_next_bounds(FAKE, 1, 12.5, out, None)] == "TTDFT_ERR_SHAPE"
+    assert L.STATUS[lib.ttdft_next_bounds(FAKE, 8, float("inf"), out, None)] == "TTDFT_ERR_BOUNDS"
+
+
+def _pass(**kw):
+    L = _lib()
+    lib = L.load()
+    Hf, H64 = kw.pop("Hf", _fake_bsr()), kw.pop("H64", _fake_bsr())
+    n = kw.pop("n", 16)
+    args = dict(X=FAKE, ldx=n, dt=0, m=8, bounds=(-3.0, 2.0, 12.5), n_conv=n,
+                lam=FAKE + (1 << 34), psi=FAKE + (1 << 35), ldpsi=n, res=FAKE + (1 << 33),
+                nxt=(C.c_double * 3)(), work=FAKE + (1 << 36), wb=None)
+    args.update(kw)
+    if args["wb"] is None:
+        args["wb"] = lib.ttdft_chfsi_pass_workspace(C.byref(Hf), C.byref(H64), n, args["dt"]) \
+            if Hf is not None else 1 << 40
+    b = (C.c_double * 3)(*args["bounds"]) if args["bounds"] is not None else None
+    return L.STATUS[lib.ttdft_chfsi_pass(
+        C.byref(Hf) if Hf is not None else None, C.byref(H64), args["X"], args["ldx"], args["dt"], n,
+        args["m"], b, args["n_conv"], args["lam"], args["psi"], args["ldpsi"], args["res"], None,
+        args["nxt"], args["work"], args["wb"], None)]
+
+
+def test_chfsi_pass_validation(lib_built):
+    L = _lib()
+    assert _pass(Hf=None) == "TTDFT_ERR_NULL"
+    assert _pass(H64=_fake_bsr(dtype=1)) == "TTDFT_ERR_DTYPE"         # Rayleigh-Ritz needs FP64
+    assert _pass(dt=2) == "TTDFT_ERR_DTYPE"                           # iterates F64 or F32
+    assert _pass(Hf=_fake_bsr(nbr=9)) == "TTDFT_ERR_SHAPE"            # not the same matrix
+    assert _pass(m=0) == "TTDFT_ERR_DEGREE"
+    assert _pass(bounds=(2.0, -3.0, 12.5)) == "TTDFT_ERR_BOUNDS"
+    assert _pass(bounds=None) == "TTDFT_ERR_NULL"
+    assert _pass(n_conv=0) == "TTDFT_ERR_SHAPE"
+    assert _pass(n_conv=17) == "TTDFT_ERR_SHAPE"
+    assert _pass(ldx=15) == "TTDFT_ERR_SHAPE"
+    assert _pass(nxt=None) == "TTDFT_ERR_NULL"
+    assert _pass(wb=1024) == "TTDFT_ERR_WORKSPACE"
+    lib = L.load()
+    H = _fake_bsr()
+    w64 = lib.ttdft_chfsi_pass_workspace(C.byref(H), C.byref(H), 16, 0)
+    w32 = lib.ttdft_chfsi_pass_workspace(C.byref(_fake_bsr(dtype=1)), C.byref(H), 16, 1)
+    assert w64 >= 8 * 64 * 16 * 8 and 0 < w32
+    assert lib.ttdft_chfsi_pass_workspace(C.byref(H), C.byref(H), 16, 2) == 0
+
+
+def _solve(**kw):
+    L = _lib()
+    lib = L.load()
+    Hf, H64 = kw.pop("Hf", _fake_bsr()), kw.pop("H64", _fake_bsr())
+    n = 16
+    args = dict(perm=FAKE, X=FAKE, ldx=n, dt=0, m=8, m_first=0, tol=1e-8, n_conv=n, max_passes=5,
+                bounds=None, k=20, lam=FAKE + (1 << 34), psi=FAKE + (1 << 35), ldpsi=n,
+                res=FAKE + (1 << 33), cap=0, nrec=C.c_int32(0), work=FAKE + (1 << 36), wb=None)
+    args.update(kw)
+    if args["wb"] is None:
+        args["wb"] = lib.ttdft_chfsi_solve_workspace(C.byref(Hf), C.byref(H64), n, args["dt"],
+                                                     0 if args["bounds"] else args["k"])
+    b = (C.c_double * 3)(*args["bounds"]) if args["bounds"] is not None else None
+    nrec = C.byref(args["nrec"]) if args["nrec"] is not None else None
+    return L.STATUS[lib.ttdft_chfsi_solve(
+        C.byref(Hf), C.byref(H64), args["perm"], args["X"], args["ldx"], args["dt"], n, args["m"],
+        args["m_first"], args["tol"], args["n_conv"], args["max_passes"], b, args["k"], 0,
+        args["lam"], args["psi"], args["ldpsi"], args["res"], None, args["cap"], nrec,
+        args["work"], args["wb"], None)]
+
+
+def test_chfsi_solve_validation(lib_built):
+    assert _solve(H64=_fake_bsr(dtype=2)) == "TTDFT_ERR_DTYPE"
+    assert _solve(perm=None) == "TTDFT_ERR_NULL"                      # Lanczos bounds need perm
+    assert _solve(nrec=None) == "TTDFT_ERR_NULL"
+    assert _solve(cap=4) == "TTDFT_ERR_NULL"                          # history NULL with a capacity
+    assert _solve(m=0) == "TTDFT_ERR_DEGREE"
+    assert _solve(m_first=-1) == "TTDFT_ERR_DEGREE"
+    assert _solve(max_passes=0) == "TTDFT_ERR_SHAPE"
+    assert _solve(k=0) == "TTDFT_ERR_SHAPE"
+    assert _solve(tol=-1.0) == "TTDFT_ERR_BOUNDS"
+    assert _solve(tol=float("nan")) == "TTDFT_ERR_BOUNDS"
+    assert _solve(bounds=(1.0, 1.0, 12.5)) == "TTDFT_ERR_BOUNDS"
+    assert _solve(wb=4096) == "TTDFT_ERR_WORKSPACE"
+    assert _solve(psi=FAKE) == "TTDFT_ERR_ALIAS"                      # Psi overlaps X
+    lib = _lib().load()
+    H = _fake_bsr()
+    w0 = lib.ttdft_chfsi_solve_workspace(C.byref(H), C.byref(H), 16, 0, 0)
+    w32 = lib.ttdft_chfsi_solve_workspace(C.byref(_fake_bsr(dtype=1)), C.byref(H), 16, 1, 0)
+    assert w0 == lib.ttdft_chfsi_pass_workspace(C.byref(H), C.byref(H), 16, 0)
+    assert w32 > lib.ttdft_chfsi_pass_workspace(C.byref(_fake_bsr(dtype=1)), C.byref(H), 16, 1)
+
+
+def test_check_finite_validation(lib_built):
+    L = _lib()
+    lib = L.load()
+    cnt = C.c_int64(-1)
+    cf = lambda A=FAKE, dt=0, rows=4, cols=4, ld=4, c=C.byref(cnt), w=FAKE * 100, wb=16: \
+        L.STATUS[lib.ttdft_check_finite(A, dt, rows, cols, ld, c, w, wb, None)]
+    assert lib.ttdft_check_finite_workspace() == 16
+    assert cf(dt=3) == "TTDFT_ERR_DTYPE"
+    assert cf(c=None) == "TTDFT_ERR_NULL"
+    assert cf(A=None) == "TTDFT_ERR_NULL"
+    assert cf(ld=3) == "TTDFT_ERR_SHAPE"
+    assert cf(rows=-1) == "TTDFT_ERR_SHAPE"
+    assert cf(wb=8) == "TTDFT_ERR_WORKSPACE"
+    assert cf(w=FAKE + 8) == "TTDFT_ERR_ALIAS"
+    assert cf(rows=0) == "TTDFT_OK" and cnt.value == 0                # empty block: no device work

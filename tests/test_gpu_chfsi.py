@@ -1,6 +1,7 @@
 """GPU parity of the convergence test of the subspace iteration (Ritz residual
-norms), the Lanczos estimates of both ends of the spectrum, and the repeated
-Algorithm 1 (Sec. 3.4) run to convergence, through the C ABI."""
+norms), the Lanczos estimates of both ends of the spectrum (with breakdown),
+one pass and the repeated Algorithm 1 (Sec. 3.4) run to convergence in the
+library, and the reporting of non-finite blocks, through the C ABI."""
 import numpy as np
 import pytest
 
@@ -53,8 +54,68 @@ def test_lanczos_bounds_bracket_the_spectrum(r, h):
     print(f"lanczos r={r} h={h}: [{th_min:.4f}, {th_max:.4f}] vs [{ev[0]:.4f}, {ev[-1]:.4f}], safe {safe:.4f}", flush=True)
     assert ev[0] - 1e-10 <= th_min <= ev[0] + 0.05 * width     # Ritz values lie inside the spectrum
     assert th_max <= ev[-1] + 1e-10 <= safe + 2e-10
-    th3 = P.lanczos_upper_bound(Hb, k=40, seed=3)
-    assert th3 == (th_max, est, safe)                           # same process, same numbers
+    again = P.lanczos_bounds(Hb, k=40, seed=3)
+    assert again == (th_max, est, safe, th_min)                 # fixed-order reductions
+
+
+@pytest.mark.parametrize("r,h,k", [(2, 1, 20), (3, 2, 40), (2, 1, 8)])
+def test_lanczos_breakdown_still_bounds_the_spectrum(r, h, k):
+    # k >= N: the Krylov space becomes invariant after at most N steps (beta
+    # vanishes); the bounds must still enclose the whole spectrum (Gershgorin)
+    torch, P = require_gpu()
+    Hc, Hb, _ = make_case(r, h, 1)
+    ev = np.linalg.eigvalsh(Hc.toarray())
+    A = np.abs(Hc.toarray())
+    rad = A.sum(axis=1) - np.diag(A)
+    g_lo, g_hi = float((Hc.diagonal() - rad).min()), float((Hc.diagonal() + rad).max())
+    th_max, est, safe, th_min = P.lanczos_bounds(Hb, k=k, seed=1)
+    print(f"breakdown r={r} k={k}: spectrum [{ev[0]:.4f}, {ev[-1]:.4f}], Gershgorin [{g_lo:.4f}, {g_hi:.4f}], "
+          f"bounds [{th_min:.4f}, {safe:.4f}] est {est:.4f}", flush=True)
+    assert np.all(np.isfinite([th_max, est, safe, th_min]))
+    assert safe >= ev[-1] - 1e-12 and est >= ev[-1] - 1e-12
+    assert th_min <= ev[0] + 1e-12
+    assert th_max <= ev[-1] + 1e-10
+    if k > Hc.shape[0]:                  # certain breakdown: the Gershgorin bounds are taken
+        assert safe >= g_hi - 1e-12 and th_min <= g_lo + 1e-12
+
+
+def test_chfsi_pass_matches_oracle_and_next_bounds():
+    # one pass through the C entry point against the oracle's filter + Rayleigh-Ritz
+    torch, P = require_gpu()
+    r, h, n, m = 10, 3, 24, 8
+    Hc, H64, X = make_case(r, h, n, seed=7)
+    bounds = (-3.0, 2.0, 12.5)
+    lam, Psi, res, rec, nxt = P.chfsi_pass(H64, H64, _blocked(P, torch, H64, X), m, bounds, n_conv=20)
+    lam_o, Psi_o = oracle.rayleigh_ritz(Hc, oracle.cheb_filter(Hc, X, m, bounds[1], bounds[2], bounds[0]))
+    lam = lam.cpu().numpy()
+    assert np.abs(lam - lam_o).max() <= 1e-10
+    ref = oracle.ritz_residuals(Hc, P.from_blocked(Psi, H64).cpu().numpy(), lam)
+    assert np.abs(res.cpu().numpy() - ref).max() <= 1e-11
+    assert rec["m"] == m and rec["max_residual"] == pytest.approx(float(ref[:20].max()), abs=1e-11)
+    assert nxt == (float(lam.min()), float(lam.max()), 12.5)
+    assert P.updated_bounds(torch.from_numpy(lam).cuda(), 12.5) == nxt[:2]
+
+
+def test_nonfinite_blocks_are_reported():
+    torch, P = require_gpu()
+    Hc, H64, X = make_case(6, 2, 8, seed=8)
+    Xb = _blocked(P, torch, H64, X)
+    assert P.check_finite(Xb) == 0
+    bad = Xb.clone()
+    bad[5, 3] = float("nan")
+    bad[70, 0] = float("inf")
+    assert P.check_finite(bad) == 2
+    assert P.check_finite(P.cast(bad, torch.float32)) == 2
+    assert P.check_finite(P.cast(bad, torch.bfloat16)) == 2
+    with pytest.raises(P.TtdftError) as err:
+        P.rayleigh_ritz(H64, bad)
+    assert err.value.name == "TTDFT_ERR_NONFINITE"
+    with pytest.raises(P.TtdftError) as err:
+        P.cholqr2(bad)
+    assert err.value.name == "TTDFT_ERR_NONFINITE"
+    with pytest.raises(P.TtdftError) as err:
+        P.chfsi_pass(H64, H64, bad, 4, (-3.0, 2.0, 12.5))
+    assert err.value.name == "TTDFT_ERR_NONFINITE"
 
 
 @pytest.mark.parametrize("hname,tol,m", [("f64", 1e-9, 12), ("f32", 1e-5, 12)])
@@ -67,6 +128,7 @@ def test_chfsi_solve_converges_to_lowest_eigenvalues(hname, tol, m):
     Xb = _blocked(P, torch, H64, X)
     lam, Psi, res, hist = P.chfsi_solve(Hf, H64, Xb, m, tol, n_conv=n_conv, max_iter=60, m_first=2 * m)
     assert not any(h.get("rank_deficient") for h in hist)
+    assert [h["pass"] for h in hist] == list(range(1, len(hist) + 1))
     print(f"chfsi {hname}: {len(hist)} passes, residual {hist[-1]['max_residual']:.3e}", flush=True)
     assert hist[-1]["max_residual"] <= tol
     lam = lam.cpu().numpy()

@@ -59,6 +59,7 @@ def test_large_two_pass_chfsi():
             err = normwise(Ys, ref)
             print(f"large: FP32 filter sampled columns, normwise error {err:.2e}", flush=True)
             assert err <= 4 * cfg.m * U32
+            eps_f = err
         del Xb
         torch.cuda.empty_cache()
         t2 = time.time()
@@ -87,9 +88,17 @@ def test_large_two_pass_chfsi():
             Xb = P.cast(Psi, torch.float32)
         del Psi
         torch.cuda.empty_cache()
-    # the second pass, started from the first pass's Ritz vectors, converges the
-    # sampled pairs: none gets worse beyond the FP32 floor of the filter
-    # (residual ~1e-5 for |H| ~ 15), and the worst one improves
+    # The second pass, started from the first pass's Ritz vectors, converges the
+    # sampled pairs down to the FP32 floor of the filter and the worst one
+    # improves.  The floor: a Ritz vector psi taken from a block whose columns
+    # carry a relative rounding error eps lies within about eps of the exact
+    # subspace, and for theta in the spectrum's range the residual
+    # (H - theta I) psi then has norm up to eps * ||H - theta I|| <= eps * (b - lambda_min),
+    # b bounding the spectrum from above and lambda_0 >= lambda_min being close
+    # to it.  eps is the normwise error of this FP32 filter, measured above on
+    # sampled columns; the factor 2 covers its spread over the other columns.
     res1, res2 = results[0][1], results[1][1]
-    assert np.all(res2 <= np.maximum(res1, 1e-5))
+    floor = 2.0 * eps_f * (b - results[0][0][0])
+    print(f"large: FP32 residual floor {floor:.2e} (eps {eps_f:.2e})", flush=True)
+    assert np.all(res2 <= np.maximum(res1, floor))
     assert res2.max() < res1.max()

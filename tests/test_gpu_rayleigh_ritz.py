@@ -210,13 +210,13 @@ def test_rayleigh_ritz_matches_oracle(r, h, n, m):
 
 
 @pytest.mark.parametrize("r,h", [(20, 3), (12, 4)])
-def test_lanczos_upper_bound(r, h):
+def test_lanczos_upper_estimates(r, h):
     # theta_max <= lambda_max (a Ritz value of a Krylov subspace); theta plus its
     # Ritz residual reaches lambda_max; the safeguarded bound lies above it
     torch, P = require_gpu()
     Hc, Hb, _ = make_case(r, h, 1)
     lmax = float(np.linalg.eigvalsh(Hc.toarray())[-1])
-    theta, est, safe = P.lanczos_upper_bound(Hb, k=30, seed=1)
+    theta, est, safe, _ = P.lanczos_bounds(Hb, k=30, seed=1)
     print(f"lambda_max {lmax:.6f}: theta {theta:.6f}, estimate {est:.6f}, safeguarded {safe:.6f}")
     assert theta <= lmax + 1e-10
     assert lmax - theta <= 0.05 * abs(lmax)

@@ -13,6 +13,7 @@ from .generator import (  # noqa: F401
     WorkloadConfig,
     lattice_hamiltonian,
     gaussian_block,
+    conditioned_block,
     positive_offsets,
     stream_rngs,
 )

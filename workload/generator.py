@@ -100,6 +100,21 @@ def gaussian_block(N: int, n: int, seed: int = 0, stream: str = "X",
     return rng.standard_normal((N, n), dtype=dtype)
 
 
+def conditioned_block(N: int, n: int, seed: int, cond: float) -> np.ndarray:
+    """N x n FP64 block G U diag(s) V^T with G ~ N(0,1) (the X stream of the
+    seed), U and V random orthogonal n x n matrices and singular factors s
+    log-spaced from 1 down to 1/cond, so the block's condition number is about
+    cond (G itself is well conditioned for N >> n).  Stands in for a filtered
+    block, whose columns are nearly dependent, as an input independent of any
+    filter implementation."""
+    G = gaussian_block(N, n, seed)
+    rng = np.random.default_rng([seed, 1])
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = np.logspace(0.0, -np.log10(cond), n)
+    return G @ ((U * s[None, :]) @ V.T)
+
+
 @dataclass(frozen=True)
 class WorkloadConfig:
     """One benchmark / parity workload: lattice, block width, degree, bounds."""
