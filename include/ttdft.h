@@ -318,7 +318,9 @@ size_t ttdft_lanczos_workspace(const ttdft_bsr *H, int32_t k);
  * include the extreme eigenvalues) T is cut at order j + 1 and bounds[1],
  * bounds[2] are raised to at least, and bounds[3] lowered to at most, the
  * Gershgorin bounds max_i (H_ii + r_i) and min_i (H_ii - r_i), r_i = sum over
- * j != i of |H_ij|, which enclose the whole spectrum.
+ * j != i of |H_ij|, which enclose the whole spectrum.  The same widening is
+ * applied when k is at least the number of real rows (the Krylov space is then
+ * invariant for certain, even where rounding keeps beta from vanishing).
  * H must be FP64.  perm: device int64 [64*n_block_rows] from ttdft_bsr_build
  * (padding rows marked -1).  bounds: host double[4].  Synchronises the stream.
  * Errors: NULL, SHAPE (k outside 1..1000), DTYPE, WORKSPACE, NONFINITE, HIP.

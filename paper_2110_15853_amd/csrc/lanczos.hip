@@ -15,6 +15,10 @@
 // steps after it would only append spurious zero rows.  The bounds are then
 // taken from T_j and widened to the Gershgorin interval of H (every eigenvalue
 // lies in some row's disc [H_ii - r_i, H_ii + r_i], r_i = sum_{j != i} |H_ij|).
+// With k at least the number of real rows the Krylov space is invariant for
+// certain, but in floating point beta need not fall below the threshold (the
+// Lanczos vectors lose orthogonality and the process runs on with copies of
+// converged Ritz values), so that case takes the Gershgorin widening as well.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -171,6 +175,16 @@ __global__ __launch_bounds__(64) void gershgorin_kernel(const int32_t *rowptr, c
   }
 }
 
+// out = number of real rows (perm >= 0), as a double (one work-group, exact
+// below 2^53)
+__global__ __launch_bounds__(1024) void count_real_kernel(const int64_t *perm, int64_t rows, double *out) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < rows; i += 1024) s += perm[i] >= 0 ? 1.0 : 0.0;
+  const double t = wg_sum(s, red);
+  if (threadIdx.x == 0) *out = t;
+}
+
 // out[0] = min(lo), out[1] = max(hi) over nb entries (one work-group)
 __global__ __launch_bounds__(1024) void minmax_kernel(const double *lo, const double *hi, int64_t nb,
                                                       double *out) {
@@ -204,17 +218,20 @@ __global__ __launch_bounds__(1024) void minmax_kernel(const double *lo, const do
 }  // namespace
 
 size_t lanczos_work_bytes(int64_t rows, int k) {
-  return (size_t)(3 * rows + 2 * (k + 2) + 4 + 2 * (rows / 64) + 2) * sizeof(double);
+  return (size_t)(3 * rows + 2 * (k + 2) + 4 + 2 * (rows / 64) + 3) * sizeof(double);
 }
 
-// work: 3 vectors + alpha[k+1] + beta[k+2] + out[4] + Gershgorin lo/hi per block row + 2
+// work: 3 vectors + alpha[k+1] + beta[k+2] + out[4] + Gershgorin lo/hi per block
+// row + 2 + the count of real rows
 hipError_t run_lanczos_bound(const ttdft_bsr &H, const int64_t *perm, int k, uint64_t seed,
                              void *work, hipStream_t s, double host_out[4], int *breakdown) {
   const int64_t rows = H.n_block_rows * 64;
   double *v0 = (double *)work, *v1 = v0 + rows, *w = v1 + rows;
   double *alpha = w + rows, *beta = alpha + (k + 1), *out = beta + (k + 2);
   double *glo = out + 4, *ghi = glo + H.n_block_rows, *gout = ghi + H.n_block_rows;
+  double *n_real = gout + 2;
   *breakdown = 0;
+  hipLaunchKernelGGL(count_real_kernel, dim3(1), dim3(1024), 0, s, perm, rows, n_real);
   const unsigned g = (unsigned)std::min<int64_t>((rows + 255) / 256, 4096);
   hipLaunchKernelGGL(lz_start_kernel, dim3(g), dim3(256), 0, s, w, rows, perm, seed);
   hipLaunchKernelGGL(lz_normalize_kernel, dim3(1), dim3(1024), 0, s, w, v0, rows, beta);
@@ -236,7 +253,9 @@ hipError_t run_lanczos_bound(const ttdft_bsr &H, const int64_t *perm, int k, uin
   // breakdown test on the host: the first beta_{j+1}, j < k, that vanishes
   // relative to the size of T_k ends the usable tridiagonal at order j + 1
   std::vector<double> ha(k), hb(k + 1);
+  double hn_real = 0.0;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  if ((e = hipMemcpy(&hn_real, n_real, sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess) return e;
   if ((e = hipMemcpy(ha.data(), alpha, k * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess) return e;
   if ((e = hipMemcpy(hb.data(), beta, (k + 1) * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess) return e;
   double scale = 0.0;
@@ -251,7 +270,7 @@ hipError_t run_lanczos_bound(const ttdft_bsr &H, const int64_t *perm, int k, uin
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
   if ((e = hipMemcpy(host_out, out, 4 * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess) return e;
-  if (k_eff < k || !(std::fabs(hb[k]) > 1e-12 * scale)) {
+  if (k_eff < k || !(std::fabs(hb[k]) > 1e-12 * scale) || (double)k >= hn_real) {
     *breakdown = 1;
     hipLaunchKernelGGL(gershgorin_kernel, dim3((unsigned)H.n_block_rows), dim3(64), 0, s,
                        H.tile_rowptr, H.tile_col, (const double *)H.vals, perm, glo, ghi);

@@ -75,7 +75,7 @@ def test_lanczos_breakdown_still_bounds_the_spectrum(r, h, k):
     assert safe >= ev[-1] - 1e-12 and est >= ev[-1] - 1e-12
     assert th_min <= ev[0] + 1e-12
     assert th_max <= ev[-1] + 1e-10
-    if k > Hc.shape[0]:                  # certain breakdown: the Gershgorin bounds are taken
+    if k >= Hc.shape[0]:                 # certain breakdown: the Gershgorin bounds are taken
         assert safe >= g_hi - 1e-12 and th_min <= g_lo + 1e-12
 
 
