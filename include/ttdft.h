@@ -181,6 +181,26 @@ ttdft_status ttdft_cheb_filter(const ttdft_bsr *H, const void *X, int64_t ldx, v
                                double a0, ttdft_dtype x_dtype, void *work, size_t work_bytes,
                                void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the filter of
+ * ttdft_cheb_filter with the same arguments except the workspace, which is a
+ * fixed device array inside the library of TTDFT_NOALLOC_SCRATCH_BYTES (64 MiB)
+ * per GPU, held from the first call on a GPU until the process ends.  The call
+ * allocates nothing.  The work block (64*n_block_rows x n_vec of x_dtype,
+ * needed for m >= 2) must fit in the array: larger problems are rejected with
+ * WORKSPACE before any device work.  The stream must belong to the current
+ * device.  Every call on one GPU shares that GPU's array, so calls that overlap
+ * in time on one GPU race; calls on one stream, one after another, do not.
+ * Results are bitwise those of ttdft_cheb_filter.  ASYNC.
+ * Errors: as ttdft_cheb_filter (WORKSPACE when the block exceeds the array),
+ * HIP (also when the array's device address cannot be looked up).
+ */
+#define TTDFT_NOALLOC_SCRATCH_BYTES (64ull << 20)
+ttdft_status ttdft_cheb_filter_noalloc(const ttdft_bsr *H, const void *X, int64_t ldx, void *Y,
+                                       int64_t ldy, int64_t n_vec, int32_t m, double a, double b,
+                                       double a0, ttdft_dtype x_dtype, void *stream);
+
 /* ---------------------------------------------------------------- precision casts */
 
 /*

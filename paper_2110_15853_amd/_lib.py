@@ -53,6 +53,8 @@ SIGNATURES = {
     "ttdft_cheb_filter_workspace": (_SZ, [_BSRP, _I64, _INT]),
     "ttdft_cheb_filter": (_INT, [_BSRP, _P, _I64, _P, _I64, _I64, _I32, _D, _D, _D, _INT, _P,
                                  _SZ, _P]),
+    "ttdft_cheb_filter_noalloc": (_INT, [_BSRP, _P, _I64, _P, _I64, _I64, _I32, _D, _D, _D, _INT,
+                                         _P]),
     "ttdft_cast": (_INT, [_P, _INT, _I64, _P, _INT, _I64, _I64, _I64, _P]),
     "ttdft_gather_rows": (_INT, [_P, _I64, _I64, _P, _I64, _I64, _I64, _P, _INT, _P]),
     "ttdft_cholqr2_workspace": (_SZ, [_I64, _I64, _INT]),

@@ -168,6 +168,19 @@ def cheb_filter(H: BsrMatrix, X: torch.Tensor, m: int, a: float, b: float, a0: f
     return out
 
 
+def cheb_filter_noalloc(H: BsrMatrix, X: torch.Tensor, m: int, a: float, b: float, a0: float,
+                        out: torch.Tensor) -> torch.Tensor:
+    """ttdft_cheb_filter_noalloc: the filter with the library's fixed device
+    scratch as its work block; `out` is caller-provided, nothing is allocated."""
+    hs = H.c_struct()
+    _lib.call("ttdft_cheb_filter_noalloc", C.byref(hs), _ptr(X), _ld(X), _ptr(out), _ld(out),
+              X.shape[1], m, a, b, a0, _code(X), _stream())
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20     # TTDFT_NOALLOC_SCRATCH_BYTES
+
+
 def _work(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 

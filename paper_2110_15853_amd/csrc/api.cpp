@@ -326,10 +326,14 @@ size_t ttdft_cheb_filter_workspace(const ttdft_bsr *H, int64_t n_vec, ttdft_dtyp
   return (size_t)H->n_block_rows * 64 * (size_t)n_vec * dtype_size(x_dtype);
 }
 
-ttdft_status ttdft_cheb_filter(const ttdft_bsr *H, const void *X, int64_t ldx, void *Y,
-                               int64_t ldy, int64_t n_vec, int32_t m, double a, double b,
-                               double a0, ttdft_dtype x_dtype, void *work, size_t work_bytes,
-                               void *stream) {
+}  // extern "C"
+
+namespace ttdft {
+// Validation of the filter's arguments shared by ttdft_cheb_filter and the
+// variant without a workspace argument; writes nothing.
+ttdft_status filter_check(const ttdft_bsr *H, const void *X, int64_t ldx, const void *Y,
+                          int64_t ldy, int64_t n_vec, int32_t m, double a, double b, double a0,
+                          ttdft_dtype x_dtype) {
   ttdft_status st = check_bsr(H);
   if (st != TTDFT_OK) return st;
   if (!valid_dtype(x_dtype) || !supported_pair(H->dtype, x_dtype))
@@ -344,14 +348,16 @@ ttdft_status ttdft_cheb_filter(const ttdft_bsr *H, const void *X, int64_t ldx, v
   if (m < 1) return fail(TTDFT_ERR_DEGREE, "degree m = %d < 1", m);
   const int64_t rows = H->n_block_rows * 64;
   const size_t elt = dtype_size(x_dtype);
-  const size_t need = ttdft_cheb_filter_workspace(H, n_vec, x_dtype);
-  if (m >= 2 && (!work || work_bytes < need))
-    return fail(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", need);
-  const Span sx = span_of(X, rows, ldx, n_vec, elt), sy = span_of(Y, rows, ldy, n_vec, elt);
-  const Span sw = m >= 2 ? span_bytes(work, need) : Span{};
-  if (overlap(sx, sy)) return fail(TTDFT_ERR_ALIAS, "Y overlaps X");
-  if (overlap(sw, sy) || overlap(sw, sx)) return fail(TTDFT_ERR_ALIAS, "workspace overlaps X or Y");
+  if (overlap(span_of(X, rows, ldx, n_vec, elt), span_of(Y, rows, ldy, n_vec, elt)))
+    return fail(TTDFT_ERR_ALIAS, "Y overlaps X");
+  return TTDFT_OK;
+}
 
+// The m launches of the filter (arguments already validated).  work holds one
+// rows x n_vec block (leading dimension n_vec) when m >= 2.
+ttdft_status filter_enqueue(const ttdft_bsr &H, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                            int64_t n_vec, int32_t m, double a, double b, double a0,
+                            ttdft_dtype x_dtype, void *work, hipStream_t s) {
   // coefficient schedule of Algorithm 1 (Sec. 3.4), FP64 on the host
   std::vector<double> alpha(m), beta(m);
   double c;
@@ -360,17 +366,37 @@ ttdft_status ttdft_cheb_filter(const ttdft_bsr *H, const void *X, int64_t ldx, v
   // last iterate lands in Y and Y_{k+1} overwrites Y_{k-1} in place.
   auto buf = [&](int k) -> void * { return (k % 2 == m % 2) ? Y : work; };
   auto ld_of = [&](int k) -> int64_t { return (k % 2 == m % 2) ? ldy : n_vec; };
-  hipStream_t s = (hipStream_t)stream;
   for (int k = 0; k < m; ++k) {
     const void *cur = k == 0 ? X : buf(k);
     const int64_t ldc = k == 0 ? ldx : ld_of(k);
     const void *prev = k == 0 ? nullptr : (k == 1 ? X : buf(k - 1));
     const int64_t ldp = k == 0 ? 0 : (k == 1 ? ldx : ld_of(k - 1));
-    hipError_t err = launch_cheb_step(*H, cur, ldc, prev, ldp, buf(k + 1), ld_of(k + 1), n_vec,
+    hipError_t err = launch_cheb_step(H, cur, ldc, prev, ldp, buf(k + 1), ld_of(k + 1), n_vec,
                                       alpha[k], c, beta[k], x_dtype, s);
     if (err != hipSuccess) return hip_status(err, "cheb_filter step");
   }
   return ok();
+}
+
+}  // namespace ttdft
+
+extern "C" {
+
+ttdft_status ttdft_cheb_filter(const ttdft_bsr *H, const void *X, int64_t ldx, void *Y,
+                               int64_t ldy, int64_t n_vec, int32_t m, double a, double b,
+                               double a0, ttdft_dtype x_dtype, void *work, size_t work_bytes,
+                               void *stream) {
+  ttdft_status st = filter_check(H, X, ldx, Y, ldy, n_vec, m, a, b, a0, x_dtype);
+  if (st != TTDFT_OK) return st;
+  const int64_t rows = H->n_block_rows * 64;
+  const size_t elt = dtype_size(x_dtype);
+  const size_t need = ttdft_cheb_filter_workspace(H, n_vec, x_dtype);
+  if (m >= 2 && (!work || work_bytes < need))
+    return fail(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", need);
+  const Span sw = m >= 2 ? span_bytes(work, need) : Span{};
+  if (overlap(sw, span_of(Y, rows, ldy, n_vec, elt)) || overlap(sw, span_of(X, rows, ldx, n_vec, elt)))
+    return fail(TTDFT_ERR_ALIAS, "workspace overlaps X or Y");
+  return filter_enqueue(*H, X, ldx, Y, ldy, n_vec, m, a, b, a0, x_dtype, work, (hipStream_t)stream);
 }
 
 size_t ttdft_check_finite_workspace(void) { return 16; }

@@ -27,6 +27,18 @@ inline bool step_ld_ok(int64_t ld, size_t elt) { return ld >= 0 && 64 * ld * (in
 void cheb_coefficients(int m, double a, double b, double a0, double *c, double *alpha,
                        double *beta);
 
+// ---- the filter's argument checks (no writes) and its m launches; work holds one
+// rows x n_vec block (leading dimension n_vec) when m >= 2
+ttdft_status filter_check(const ttdft_bsr *H, const void *X, int64_t ldx, const void *Y,
+                          int64_t ldy, int64_t n_vec, int32_t m, double a, double b, double a0,
+                          ttdft_dtype x_dtype);
+ttdft_status filter_enqueue(const ttdft_bsr &H, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                            int64_t n_vec, int32_t m, double a, double b, double a0,
+                            ttdft_dtype x_dtype, void *work, hipStream_t s);
+// set the thread-local error string and return s
+ttdft_status api_fail(ttdft_status s, const char *msg);
+ttdft_status api_ok();
+
 // ---- fused BSR SpMM + Chebyshev recurrence epilogue (one degree step)
 hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, const void *Yp,
                             int64_t ldp, void *Yo, int64_t ldo, int64_t n_vec, double alpha,

@@ -82,6 +82,31 @@ def test_filter_validation(lib_built, kw, status):
     assert L.load().ttdft_last_error().decode() != ""
 
 
+def test_filter_noalloc_validation(lib_built):
+    # the same argument checks as ttdft_cheb_filter, and a work block larger than
+    # the fixed 64 MiB scratch is rejected before any device work
+    L = _lib()
+    lib = L.load()
+
+    def call(H=None, X=FAKE, Y=FAKE * 1000, n=16, m=10, a0=-3.0, dt=0):
+        H = H if H is not None else _fake_bsr()
+        return L.STATUS[lib.ttdft_cheb_filter_noalloc(C.byref(H), X, n, Y, n, n, m, 2.0, 12.5, a0,
+                                                      dt, None)]
+
+    assert call(X=None) == "TTDFT_ERR_NULL"
+    assert call(a0=2.0) == "TTDFT_ERR_BOUNDS"
+    assert call(m=0) == "TTDFT_ERR_DEGREE"
+    assert call(Y=FAKE + 8) == "TTDFT_ERR_ALIAS"
+    assert call(dt=1) == "TTDFT_ERR_DTYPE"
+    # 2048 block rows x 64 rows x 1024 vectors x 8 bytes = 1 GiB > 64 MiB
+    big = _fake_bsr(nbr=2048)
+    assert call(H=big, n=1024, Y=FAKE * 100000) == "TTDFT_ERR_WORKSPACE"
+    assert "scratch" in lib.ttdft_last_error().decode()
+    # the limit is 64 MiB = 128 block rows x 64 rows x 1024 vectors x 8 bytes: one
+    # block row more is rejected (the accepted side runs on the GPU test)
+    assert call(H=_fake_bsr(nbr=129), n=1024, Y=FAKE * 100000) == "TTDFT_ERR_WORKSPACE"
+
+
 def test_step_and_cast_validation(lib_built):
     L = _lib()
     lib = L.load()
