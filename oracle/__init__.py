@@ -16,6 +16,7 @@ from .chfsi import (  # noqa: F401
     sigma_sequence,
     cheb_filter,
     cheb_filter_scaled,
+    cheb_filter_schedule,
     cheb_filter_adjoint,
     orth,
     cholqr2,

@@ -106,6 +106,33 @@ def cheb_filter_scaled(H, X, m: int, a: float, b: float, a0: float):
     return y
 
 
+def cheb_filter_schedule(H_early, H_late, m_late: int, X, m: int, a: float, b: float,
+                         a0: float):
+    """The filter with a precision schedule: the scaled iterates of
+    cheb_filter_scaled, where the degree steps k = 0 .. m - m_late - 1 (the step
+    forming Y_{k+1} from Y_k) take their product with H_early and the last
+    m_late steps with H_late.  With H_early = H_late it is the filter of Sec. 3.4;
+    here the two are the same Hamiltonian rounded to two precisions, so every
+    step uses the same coefficients (ratios of T_j(tau)) and only the matrix
+    changes with the step."""
+    if m < 1:
+        raise ValueError("degree m must be >= 1")
+    if not 0 <= m_late <= m:
+        raise ValueError("m_late must lie in 0 .. m")
+    e, c, tau = filter_parameters(a, b, a0)
+    X = np.asarray(X, dtype=np.float64)
+    t = [float(chebyshev_T(j, tau)) for j in range(m + 1)]
+
+    def hs(k, V):
+        H = H_early if k < m - m_late else H_late
+        return (H @ V - c * V) / e
+
+    y_prev, y = X, hs(0, X) / t[1]
+    for k in range(1, m):
+        y_prev, y = y, (2.0 * t[k] / t[k + 1]) * hs(k, y) - (t[k - 1] / t[k + 1]) * y_prev
+    return y
+
+
 def cheb_filter_adjoint(H, X, dY, m: int, a: float, b: float, a0: float,
                         chunk: int = 1 << 16):
     """Gradients of L = <dY, Y> for Y = cheb_filter(H, X, ...).

@@ -94,6 +94,69 @@ def test_filter_config1_scaled_vs_definition():
     assert np.linalg.norm(Y1 - Y2) / np.linalg.norm(Y1) < 1e-14
 
 
+def u_closed(n, y):
+    """Chebyshev U_n from its trigonometric / hyperbolic closed form (U_-1 = 0)."""
+    y = np.asarray(y, dtype=np.float64)
+    if n < 0:
+        return np.zeros_like(y)
+    out = np.empty_like(y)
+    inside = np.abs(y) < 1
+    th = np.arccos(y[inside])
+    out[inside] = np.sin((n + 1) * th) / np.sin(th)
+    yo = y[~inside]
+    ph = np.arccosh(np.abs(yo))
+    out[~inside] = np.sign(yo) ** n * np.sinh((n + 1) * ph) / np.sinh(ph)
+    return out
+
+
+def schedule_closed_form(lam, mu, m, m_late, a=A, b=B, a0=A0):
+    """Scalar filter value when the first s = m - m_late degree steps use the
+    eigenvalue lam and the rest mu (commuting matrices): the unscaled iterate
+    is T_k(x) up to k = s, x = (lam - c)/e; after that the recurrence with
+    y = (mu - c)/e continues from (T_{s-1}(x), T_s(x)), and any solution of
+    f_{j+1} = 2 y f_j - f_{j-1} is f_0 T_j(y) + (f_1 - y f_0) U_{j-1}(y)."""
+    e, c = (b - a) / 2, (b + a) / 2
+    x, y = (lam - c) / e, (mu - c) / e
+    tm = t_closed(m, np.array([(a0 - c) / e]))[0]
+    s = m - m_late
+    if s == 0:
+        return t_closed(m, y) / tm
+    f0, f1 = t_closed(s - 1, x), t_closed(s, x)
+    j = m - s + 1
+    return (f0 * t_closed(j, y) + (f1 - y * f0) * u_closed(j - 1, y)) / tm
+
+
+@pytest.mark.parametrize("m,m_late", [(1, 0), (1, 1), (2, 1), (10, 0), (10, 3), (10, 10), (20, 4),
+                                      (20, 19), (7, 1)])
+def test_schedule_commuting_matrices_closed_form(m, m_late):
+    # two symmetric matrices with the same eigenvectors: the scheduled filter
+    # acts on each eigenvector by the scalar closed form above
+    rng = np.random.default_rng(m * 100 + m_late)
+    n = 40
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.sort(rng.uniform(-12.0, 11.0, n))
+    mu = lam + rng.uniform(-0.3, 0.3, n)
+    He, Hl = (V * lam) @ V.T, (V * mu) @ V.T
+    X = rng.standard_normal((n, 5))
+    Y = oracle.cheb_filter_schedule(He, Hl, m_late, X, m, A, B, A0)
+    ref = V @ (schedule_closed_form(lam, mu, m, m_late)[:, None] * (V.T @ X))
+    assert np.linalg.norm(Y - ref) / np.linalg.norm(ref) < 1e-12
+
+
+def test_schedule_reduces_to_the_filter():
+    # no switch, or the same matrix on both sides: the plain filter (closed form)
+    H, N = small_h(5, 2)
+    X = workload.gaussian_block(N, 4, 5)
+    lam, V = np.linalg.eigh(H.toarray())
+    Hd = sp.diags(np.linspace(-3.0, 9.0, N)).tocsr()
+    for m, m_late, He, Hl in ((10, 0, H, Hd), (10, 10, Hd, H), (12, 5, H, H), (1, 1, Hd, H)):
+        Y = oracle.cheb_filter_schedule(He, Hl, m_late, X, m, A, B, A0)
+        ref = V @ (p_of(lam, m)[:, None] * (V.T @ X))
+        assert np.linalg.norm(Y - ref) / np.linalg.norm(ref) < 1e-13
+    with pytest.raises(ValueError):
+        oracle.cheb_filter_schedule(H, H, 11, X, 10, A, B, A0)
+
+
 def test_filter_degree_one():
     H, N = small_h()
     X = workload.gaussian_block(N, 3, 2)
