@@ -9,7 +9,7 @@ adjoint on the adjoint workload, the reduced-precision filters against FP64 and
 the CPU oracle's rate.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                    [--precision f64|f32|bf16] [--no-cpu-baseline] [--no-rr]
+                    [--precision f64|f32|bf16|bf16x3] [--no-cpu-baseline] [--no-rr]
                     [--no-mixed] [--no-adjoint] [--solve] [--calib-copy]
 """
 from __future__ import annotations
@@ -50,42 +50,90 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(Hc, X, cfg, n_cols):
-    """The FP64 oracle (SciPy CSR, single thread) on a column sample of the
-    same workload; the filter is column-independent, so the per-column work is
-    the same as in the full run."""
+def cpu_baseline(Hc, X, cfg, n_cols, threads=None):
+    """The FP64 oracle (SciPy CSR) on a column sample of the same workload, as
+    it stands: first on one core (n_cols columns), then on all host cores with
+    one thread per n_cols-column slice (the filter is column-independent, so
+    the slices are independent oracle runs; SciPy's sparse product and NumPy's
+    array arithmetic release the GIL).  Reported as algorithmic GFLOP/s."""
     import oracle
-    Xs = np.ascontiguousarray(X[:, :n_cols])
+    from concurrent.futures import ThreadPoolExecutor
+    threads = threads or min(16, os.cpu_count() or 1)
+
+    def run(j):
+        Xs = np.ascontiguousarray(X[:, j * n_cols:(j + 1) * n_cols])
+        oracle.cheb_filter(Hc, Xs, cfg.m, cfg.a, cfg.b, cfg.a0)
+
     t0 = time.perf_counter()
-    oracle.cheb_filter(Hc, Xs, cfg.m, cfg.a, cfg.b, cfg.a0)
-    dt = time.perf_counter() - t0
-    flops = 2.0 * Hc.nnz * n_cols * cfg.m
-    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_cols} of {cfg.n} columns, full m={cfg.m} filter, SciPy CSR FP64 "
-                      f"({dt:.1f} s); algorithmic flops 2*nnz*cols*m",
+    run(0)
+    dt1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(run, range(threads)))
+    dtn = time.perf_counter() - t0
+    flops1 = 2.0 * Hc.nnz * n_cols * cfg.m
+    return {"value": flops1 * threads / dtn / 1e9, "unit": "GFLOP/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{threads * n_cols} of {cfg.n} columns as {threads} threads x {n_cols} columns, "
+                      f"full m={cfg.m} filter, SciPy CSR FP64 ({dtn:.1f} s); algorithmic flops "
+                      f"2*nnz*cols*m",
+            "one_core": {"value": flops1 / dt1 / 1e9, "sample": f"{n_cols} columns ({dt1:.1f} s)"},
             "host_cpus": os.cpu_count(), "host": platform.processor() or platform.machine()}
 
 
-def mixed_precision_report(P, torch, ip, ix, d, cfg, H64, Xb64, keep_frac=1800 / 2048, reps=3):
-    """Low-precision filters (FP32; BF16 H with FP32 iterates; bf16x3 split
-    products with FP32 iterates) followed by the
-    FP64 Rayleigh-Ritz with FP64 H, against the FP64 pipeline from the same
-    start block: timing of the filters, and the error of the lowest Ritz values
-    and the largest principal angle between the Ritz subspaces, from a random
-    start (cold) and from the FP64 Ritz vectors of one previous pass (warm)."""
+STEP_KERNEL = {"f64": "cheb_step_mfma<double>", "f32": "cheb_step_mfma<float>",
+               "bf16": "cheb_step_bf16<float, false>", "bf16x3": "cheb_step_bf16<float, true>"}
+
+
+def step_roofline(prec, alg_flops, alg_bytes, launch_s, traffic=None):
+    """Roofline entry of one step-kernel launch.  FP64 and FP32 tiles are bound
+    by the matrix cores (arithmetic intensity 43.6 flop/B against ridges of 9.8
+    and 19.7); BF16 tiles with FP32 iterates are bound by HBM (ridge about 315
+    flop/B), so they are reported as algorithmic bytes per launch time."""
+    if prec in ("f64", "f32"):
+        ach = alg_flops / launch_s / 1e12
+        return {"bound": "mfma", "kernel": STEP_KERNEL[prec], "achieved": round(ach, 3),
+                "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s", "frac": round(ach / PEAK_TFLOPS[prec], 4),
+                "traffic": traffic}
+    ach = alg_bytes / launch_s / 1e9
+    return {"bound": "hbm", "kernel": STEP_KERNEL[prec], "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic}
+
+
+def issued_flops(H, prec):
+    """Matrix-core flop issued per vector by one step launch: FP64/FP32 tiles
+    issue the 16x4 fragments whose mask bit is set (2*64 flop each per vector);
+    BF16 tiles issue the 16x32 fragments holding any set 16x4 sub-block (2*512
+    flop each), three times for the bf16x3 split products."""
+    fm = H.frag_mask.cpu().numpy().view(np.uint64)
+    if prec in ("f64", "f32"):
+        return 2.0 * 64 * int(np.unpackbits(fm.view(np.uint8)).sum())
+    bits = np.unpackbits(fm.view(np.uint8), bitorder="little").reshape(-1, 64)   # bit 4*kk4 + mb
+    frag = bits.reshape(-1, 2, 8, 4).any(axis=2)                                   # [tile, kk, mb]
+    return 2.0 * 512 * int(frag.sum()) * (3 if prec == "bf16x3" else 1)
+
+
+def mixed_precision_report(P, torch, ip, ix, d, cfg, H64, Xb64, keep_frac=1800 / 2048, reps=3,
+                           m_late=(4, 8)):
+    """Low-precision filters followed by the FP64 Rayleigh-Ritz with FP64 H,
+    against the FP64 pipeline from the same start block (the FP64 pipeline is
+    itself checked against the oracle at this size by the tests): FP32 tiles;
+    BF16 tiles; bf16x3 split products; and the precision schedules BF16 tiles
+    for the first m - m_late steps then FP32 or bf16x3 tiles for the last
+    m_late, for each m_late given (FP32 iterates throughout).  For each: the filter time, its
+    roofline entry, and the error of the lowest Ritz values and the largest
+    principal angle between the Ritz subspaces, from a random start (cold) and
+    from the FP64 Ritz vectors of one previous pass (warm)."""
     keep = int(round(keep_frac * cfg.n))
-    out = {"keep": keep}
+    out = {"keep": keep, "m_late": list(m_late), "reference": "GPU FP64 pipeline (filter + Rayleigh-Ritz)"}
 
-    def filt(H, X):
-        return P.cheb_filter(H, X, cfg.m, cfg.a, cfg.b, cfg.a0)
-
-    def time_filter(H, X):
-        Y = filt(H, X)
+    def time_filter(fn, X):
+        Y = fn(X)
         torch.cuda.synchronize()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         ev[0].record()
         for _ in range(reps):
-            filt(H, X)
+            fn(X)
         ev[1].record()
         torch.cuda.synchronize()
         return ev[0].elapsed_time(ev[1]) / reps, Y
@@ -94,27 +142,45 @@ def mixed_precision_report(P, torch, ip, ix, d, cfg, H64, Xb64, keep_frac=1800 /
         S = torch.linalg.svdvals((U.T @ V).cpu())
         return float(torch.arccos(torch.clamp(S.min(), -1.0, 1.0)))
 
-    t64, _ = time_filter(H64, Xb64)
+    f64 = lambda X: P.cheb_filter(H64, X, cfg.m, cfg.a, cfg.b, cfg.a0)
+    t64, _ = time_filter(f64, Xb64)
     out["f64_filter_ms"] = round(t64, 3)
-    lam_c, psi_c = P.rayleigh_ritz(H64, filt(H64, Xb64))
+    lam_c, psi_c = P.rayleigh_ritz(H64, f64(Xb64))
     Xw = psi_c.clone()
-    lam_w, psi_w = P.rayleigh_ritz(H64, filt(H64, Xw))
-    for name, hdt in (("f32", torch.float32), ("bf16", torch.bfloat16), ("bf16x3", "bf16x3")):
-        H = P.bsr_build(ip, ix, d, cfg.r, dtype=hdt, device="cuda")
+    lam_w, psi_w = P.rayleigh_ritz(H64, f64(Xw))
+    tiles = {"f32": P.bsr_astype(H64, torch.float32), "bf16": P.bsr_astype(H64, torch.bfloat16),
+             "bf16x3": P.bsr_astype(H64, "bf16x3")}
+    elt = 4
+    x_bytes = 3.0 * H64.rows * cfg.n * elt
+    nnz = len(d)
+    runs = [("f32", "f32", 0), ("bf16", "bf16", 0), ("bf16x3", "bf16x3", 0)]
+    for ml in m_late:
+        runs += [(f"bf16x{cfg.m - ml}+f32x{ml}", "f32", ml), (f"bf16x{cfg.m - ml}+bf16x3x{ml}", "bf16x3", ml)]
+    for name, late, ml in runs:
+        early = name.split("x")[0] if "+" in name else name
+        He, Hl = tiles[early], tiles[late]
+        fn = lambda X, He=He, Hl=Hl, ml=ml: P.cheb_filter_schedule(He, Hl, ml, X, cfg.m, cfg.a, cfg.b, cfg.a0)
         Xl = P.cast(Xb64, torch.float32)
-        tl, _ = time_filter(H, Xl)
-        rec = {"filter_ms": round(tl, 3), "speedup_vs_f64_filter": round(t64 / tl, 3),
-               "alg_gflops": round(2.0 * len(d) * cfg.n * cfg.m / (tl / 1e3) / 1e9, 1)}
+        tl, _ = time_filter(fn, Xl)
+        steps = [(early, cfg.m - ml), (late, ml)] if ml else [(early, cfg.m)]
+        rec = {"filter_ms": round(tl, 3), "steps": {k: v for k, v in steps if v},
+               "speedup_vs_f64_filter": round(t64 / tl, 3),
+               "alg_gflops": round(2.0 * nnz * cfg.n * cfg.m / (tl / 1e3) / 1e9, 1)}
+        if ml == 0:
+            hb = tiles[early].vals.numel() * tiles[early].vals.element_size()
+            rec["roofline"] = step_roofline(early, 2.0 * nnz * cfg.n, hb + x_bytes, tl / 1e3 / cfg.m)
+            rec["roofline"]["alg_bytes_per_launch"] = hb + x_bytes
         for regime, X0, lam_ref, psi_ref in (("cold", Xl, lam_c, psi_c),
                                              ("warm", P.cast(Xw, torch.float32), lam_w, psi_w)):
-            lam, psi = P.rayleigh_ritz(H64, filt(H, X0))
+            lam, psi = P.rayleigh_ritz(H64, fn(X0))
             err = float((lam[:keep] - lam_ref[:keep]).abs().max())
             rec[regime] = {"max_ritz_err_Ha": err, "max_angle_rad": angle(psi_ref[:, :keep], psi[:, :keep]),
                            "meets_1e-6_Ha": err <= 1e-6}
         out[name] = rec
-        del H
         torch.cuda.empty_cache()
         log(f"mixed {name}: {rec}")
+    del tiles
+    torch.cuda.empty_cache()
     return out
 
 
@@ -323,7 +389,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="lattice60_h4_n2048_m20")
-    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cols", type=int, default=8)
     ap.add_argument("--no-rr", action="store_true", help="time the filter alone")
@@ -362,8 +428,10 @@ def main():
     t0 = time.perf_counter()
     ip, ix, d, N = workload.lattice_hamiltonian(cfg.r, cfg.h, cfg.seed)
     log(f"H generated: N={N} nnz={len(d)} ({time.perf_counter() - t0:.1f} s)")
-    hdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[args.precision]
-    xdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}[args.precision]
+    hdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16,
+           "bf16x3": "bf16x3"}[args.precision]
+    xdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32,
+           "bf16x3": torch.float32}[args.precision]
     H = P.bsr_build(ip, ix, d, cfg.r, dtype=hdt, device="cuda")
     log(f"BSR built: {H.n_block_rows} block rows, {H.n_tiles} tiles")
     X = workload.gaussian_block(N, cfg.n, cfg.seed)
@@ -422,21 +490,19 @@ def main():
     nnz = len(d)
     n = cfg.n
     alg_flops_launch = 2.0 * nnz * n                      # one H*Y_k product
-    # matrix-core work actually issued: 16x4 sub-blocks whose fragment-mask bit is set
-    frag_bits = int(sum(bin(int(v)).count("1") for v in H.frag_mask.cpu().numpy().view(np.uint64)))
-    issued_flops_launch = 2.0 * frag_bits * 64 * n
+    issued_flops_launch = issued_flops(H, args.precision) * n
     elt = Xb.element_size()
     h_bytes = H.vals.numel() * H.vals.element_size() + 4 * (H.n_tiles + H.n_block_rows + 1)
     alg_bytes_launch = h_bytes + 3.0 * H.rows * n * elt    # read Y_k, Y_{k-1}, write Y_{k+1}
     filt_s = float(np.mean(filt_ms)) / 1e3
     launch_s = filt_s / cfg.m
     value = alg_flops_launch * cfg.m / filt_s / 1e9
-    peak = PEAK_TFLOPS[args.precision]
-    achieved = alg_flops_launch / launch_s / 1e12
     counted = COUNTED_TRAFFIC.get((args.precision, cfg.name))
     traffic = None
     if counted and counted["kernel_sha256_16"] == kernel_source_sha16():
         traffic = counted["read_bytes"] + counted["write_bytes"]
+    roofline = step_roofline(args.precision, alg_flops_launch, alg_bytes_launch, launch_s, traffic)
+    peak = PEAK_TFLOPS["bf16" if args.precision == "bf16x3" else args.precision]
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -448,7 +514,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.precision if args.precision != "bf16" else "bf16xf32",
+        "dtype": {"bf16": "bf16xf32", "bf16x3": "bf16x3xf32"}.get(args.precision, args.precision),
         "data": "synthetic",
         "config": {"workload": cfg.name, "N": N, "rows_blocked": H.rows, "n_vec": n, "m": cfg.m,
                    "h": cfg.h, "nnz": nnz, "tiles": H.n_tiles, "fill": nnz / (H.n_tiles * 4096),
@@ -459,11 +525,7 @@ def main():
         "hbm_gbs_algorithmic": round(alg_bytes_launch / launch_s / 1e9, 1),
         "issued_tflops": round(issued_flops_launch / launch_s / 1e12, 2),
         "issued_frac": round(issued_flops_launch / launch_s / 1e12 / peak, 4),
-        "roofline": {"bound": "mfma", "kernel": "cheb_step_mfma<double>" if args.precision == "f64"
-                     else ("cheb_step_mfma<float>" if args.precision == "f32"
-                           else "cheb_step_bf16_pipe<float>"),
-                     "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": traffic,
+        "roofline": {**roofline,
                      "per_launch": {"alg_flops": alg_flops_launch, "alg_bytes": alg_bytes_launch,
                                     "issued_flops": issued_flops_launch,
                                     "avg_launch_ms": round(launch_s * 1e3, 4),

@@ -73,9 +73,14 @@ typedef enum { TTDFT_F64 = 0, TTDFT_F32 = 1, TTDFT_BF16 = 2, TTDFT_BF16_SPLIT = 
  * nearby lattice sites (locality of the localized Tucker basis, Sec. 4.1).  Rows
  * are grouped by 4x4x4 lattice blocks into block rows of 64; each stored tile is
  * the dense 64x64 coupling between two blocks.  Site (i, j, k) of the lattice
- * lies in block ((i/4)*nb + j/4)*nb + k/4, nb = ceil(r/4), at local position
+ * lies in block (i/4, j/4, k/4) at local position
  * 16*(2*((i%4)/2) + (j%4)/2) + 4*(2*(i%2) + j%2) + k%4: sixteen consecutive
- * rows are a 2x2x4 box, four consecutive columns a line along k.
+ * rows are a 2x2x4 box, four consecutive columns a line along k.  The blocks
+ * are numbered by 2x2x2 patches: each complete patch of blocks takes eight
+ * consecutive numbers (its blocks in (i, j, k) order, patches in lexicographic
+ * order), and the blocks of the incomplete patches at the far faces (an odd
+ * number of blocks per axis) come last.  perm from ttdft_bsr_build records the
+ * resulting row order.
  */
 typedef struct {
   int64_t n_block_rows;        /* number of 64-row blocks; padded row count is 64*n_block_rows */
@@ -84,13 +89,16 @@ typedef struct {
                                   tile_rowptr[B] .. tile_rowptr[B+1]-1                         */
   const int32_t *tile_col;     /* device [n_tiles]: block column of each tile, ascending in a row */
   const void *vals;            /* device [n_tiles*4096] values, dtype below, each tile in
-                                  matrix-core fragment order: entry (i, j) of tile t at
-                                  t*4096 + 64*(4*(j/4) + i/16) + 16*(j%4) + i%16 (the 16x4
-                                  sub-block of rows 16*(i/16).., columns 4*(j/4).. is 64
-                                  consecutive values, column-major inside).  BF16_SPLIT:
-                                  [n_tiles*8192] bf16, tile t = the 4096 hi values at
-                                  t*8192 + p, then the 4096 lo values at t*8192 + 4096 + p
-                                  (p the fragment-order position above)                 */
+                                  the matrix-core fragment order of its type.  F64 and F32:
+                                  entry (i, j) of tile t at t*4096 + 64*(4*(j/4) + i/16) +
+                                  16*(j%4) + i%16 (the 16x4 sub-block of rows 16*(i/16)..,
+                                  columns 4*(j/4).. is 64 consecutive values, column-major
+                                  inside).  BF16: at t*4096 + 512*(4*(j/32) + i/16) +
+                                  8*(i%16 + 16*((j%32)/8)) + j%8 (the 16x32 fragment of the
+                                  bf16 op, 8 consecutive columns of one row per 16 bytes).
+                                  BF16_SPLIT: [n_tiles*8192] bf16, tile t = the 4096 hi
+                                  values at t*8192 + p, then the 4096 lo values at
+                                  t*8192 + 4096 + p (p the BF16 position above)        */
   ttdft_dtype dtype;
   const uint64_t *frag_mask;   /* device [n_tiles] or NULL: bit (4*kk + mb) set when the 16x4
                                   sub-block rows 16mb..16mb+15, columns 4kk..4kk+3 of the tile
@@ -126,7 +134,8 @@ ttdft_status ttdft_bsr_build_size(int32_t r, int32_t blk, const int64_t *rowptr,
  * with the sizes from ttdft_bsr_plan):
  *   tile_rowptr[n_block_rows+1], tile_col[n_tiles],
  *   vals[n_tiles*4096] of dtype (F64, F32 or BF16; rounding to nearest even), in
- *   the fragment order of ttdft_bsr.vals ([n_tiles*8192] for BF16_SPLIT),
+ *   the fragment order of ttdft_bsr.vals for that dtype ([n_tiles*8192] for
+ *   BF16_SPLIT),
  *   perm[64*n_block_rows]: blocked row -> natural row, or -1 for a padding row,
  *   entry_slot[nnz] (may be NULL): flat index into vals of each CSR entry (of
  *   its hi value for BF16_SPLIT; lo at +4096),
@@ -182,6 +191,28 @@ ttdft_status ttdft_cheb_filter(const ttdft_bsr *H, const void *X, int64_t ldx, v
                                void *stream);
 
 /*
+ * Step 1 of Algorithm 1 with a precision schedule: the filter of
+ * ttdft_cheb_filter (same coefficients, same iterates in x_dtype) where the
+ * first m - m_late degree steps take their product with H_early and the last
+ * m_late steps with H_late, normally the same Hamiltonian in a cheaper and a
+ * more accurate tile format (e.g. BF16 then FP32, or BF16 then BF16_SPLIT, all
+ * with F32 iterates).  An error made in an early step is damped in the
+ * unwanted directions by the later steps (Sec. 3.4: the filter suppresses the
+ * unwanted spectrum), so the accurate format is needed only at the end.  Both
+ * matrices must describe the same blocked pattern (same n_block_rows and
+ * n_tiles, same tile_rowptr / tile_col content) and each must support
+ * x_dtype.  m_late = 0 is ttdft_cheb_filter with H_early, m_late = m with
+ * H_late.  work as for ttdft_cheb_filter.  ASYNC.
+ * Errors: as ttdft_cheb_filter; SHAPE when the two matrices differ in size;
+ * DEGREE when m_late lies outside 0 .. m.
+ */
+ttdft_status ttdft_cheb_filter_schedule(const ttdft_bsr *H_early, const ttdft_bsr *H_late,
+                                        int32_t m_late, const void *X, int64_t ldx, void *Y,
+                                        int64_t ldy, int64_t n_vec, int32_t m, double a, double b,
+                                        double a0, ttdft_dtype x_dtype, void *work,
+                                        size_t work_bytes, void *stream);
+
+/*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the filter of
  * ttdft_cheb_filter with the same arguments except the workspace, which is a
@@ -215,10 +246,23 @@ ttdft_status ttdft_cast(const void *src, ttdft_dtype src_dtype, int64_t lds, voi
 /*
  * FP64 tile values (n_tiles*4096, fragment order, e.g. the vals of an F64
  * ttdft_bsr) to the BF16_SPLIT layout (n_tiles*8192 bf16: per tile the hi
- * values, then the lo values), on the device.  src, dst: device, not
- * overlapping.  ASYNC.  Errors: NULL, SHAPE (n_tiles < 0), ALIAS, HIP.
+ * values, then the lo values, in the BF16 fragment order), on the device.
+ * Same as ttdft_convert_tiles(src, F64, n_tiles, dst, BF16_SPLIT).  src, dst:
+ * device, not overlapping.  ASYNC.  Errors: NULL, SHAPE (n_tiles < 0), ALIAS, HIP.
  */
 ttdft_status ttdft_split_bf16(const double *src, int64_t n_tiles, void *dst, void *stream);
+
+/*
+ * Tile values of a ttdft_bsr converted to another tile type on the device, in
+ * the fragment order of the destination type (see ttdft_bsr.vals): F64 or F32
+ * source (n_tiles*4096) to F32 (rounded, same order), BF16 (bf16(fp32(h)),
+ * reordered) or BF16_SPLIT (hi and lo, reordered; n_tiles*8192 bf16).  The
+ * pattern arrays of the source matrix serve the converted one unchanged.
+ * src, dst: device, not overlapping.  ASYNC.
+ * Errors: NULL, SHAPE (n_tiles < 0), DTYPE (other pairs), ALIAS, HIP.
+ */
+ttdft_status ttdft_convert_tiles(const void *src, ttdft_dtype src_dtype, int64_t n_tiles, void *dst,
+                                 ttdft_dtype dst_dtype, void *stream);
 
 /*
  * Row gather: dst[i, :] = src[perm[i], :] for perm[i] >= 0 and 0 for
@@ -436,7 +480,8 @@ size_t ttdft_cheb_filter_backward_workspace(const ttdft_bsr *H, int64_t n_vec, i
  *   are written as 0.
  * X, dY: device 64*n_block_rows x n_vec of x_dtype (ldx, lddy).  dX: same shape
  * and dtype (lddx), overlapping neither X, dY nor work.  dH_vals: device
- * [n_tiles*4096] in the layout of the tile values (fragment order), FP64 when
+ * [n_tiles*4096] in the layout of the tile values of H (the fragment order of
+ * H's dtype: 16x4 for F64 / F32 tiles, 16x32 for BF16 tiles), FP64 when
  * x_dtype is F64 and FP32 otherwise.  mask: device
  * [n_tiles*64] from ttdft_bsr_build, or NULL (every tile entry written).  The
  * result does not depend on ckpt_every (bitwise).  ASYNC.

@@ -11,6 +11,9 @@ from .api import (  # noqa: F401
     bsr_build,
     cast,
     cheb_filter,
+    cheb_filter_schedule,
+    cheb_filter_noalloc,
+    NOALLOC_SCRATCH_BYTES,
     cheb_step,
     from_blocked,
     to_blocked,

@@ -53,6 +53,8 @@ SIGNATURES = {
     "ttdft_cheb_filter_workspace": (_SZ, [_BSRP, _I64, _INT]),
     "ttdft_cheb_filter": (_INT, [_BSRP, _P, _I64, _P, _I64, _I64, _I32, _D, _D, _D, _INT, _P,
                                  _SZ, _P]),
+    "ttdft_cheb_filter_schedule": (_INT, [_BSRP, _BSRP, _I32, _P, _I64, _P, _I64, _I64, _I32, _D,
+                                          _D, _D, _INT, _P, _SZ, _P]),
     "ttdft_cheb_filter_noalloc": (_INT, [_BSRP, _P, _I64, _P, _I64, _I64, _I32, _D, _D, _D, _INT,
                                          _P]),
     "ttdft_cast": (_INT, [_P, _INT, _I64, _P, _INT, _I64, _I64, _I64, _P]),
@@ -74,6 +76,7 @@ SIGNATURES = {
     "ttdft_ritz_residuals_workspace": (_SZ, [_BSRP, _I64]),
     "ttdft_ritz_residuals": (_INT, [_BSRP, _P, _I64, _P, _I64, _P, _P, _SZ, _P]),
     "ttdft_split_bf16": (_INT, [_P, _I64, _P, _P]),
+    "ttdft_convert_tiles": (_INT, [_P, _INT, _I64, _P, _INT, _P]),
     "ttdft_fermi_level_workspace": (_SZ, []),
     "ttdft_fermi_level": (_INT, [_P, _I64, C.c_double, C.c_double, _P, _P, _P, _SZ, _P]),
     "ttdft_density_matrix": (_INT, [_BSRP, _P, _I64, _P, _I64, _P, _P, _P]),

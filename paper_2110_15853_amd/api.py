@@ -168,6 +168,25 @@ def cheb_filter(H: BsrMatrix, X: torch.Tensor, m: int, a: float, b: float, a0: f
     return out
 
 
+def cheb_filter_schedule(H_early: BsrMatrix, H_late: BsrMatrix, m_late: int, X: torch.Tensor,
+                         m: int, a: float, b: float, a0: float, out: torch.Tensor = None,
+                         work: torch.Tensor = None) -> torch.Tensor:
+    """ttdft_cheb_filter_schedule: the filter with the first m - m_late steps on
+    H_early and the last m_late steps on H_late (same pattern, other precision)."""
+    he, hl = H_early.c_struct(), H_late.c_struct()
+    n = X.shape[1]
+    code = _code(X)
+    need = _lib.load().ttdft_cheb_filter_workspace(C.byref(he), n, code)
+    if out is None:
+        out = torch.empty((H_early.rows, n), dtype=X.dtype, device=X.device)
+    if work is None and m >= 2:
+        work = torch.empty(need, dtype=torch.uint8, device=X.device)
+    _lib.call("ttdft_cheb_filter_schedule", C.byref(he), C.byref(hl), m_late, _ptr(X), _ld(X),
+              _ptr(out), _ld(out), n, m, a, b, a0, code, _ptr(work),
+              work.numel() if work is not None else 0, _stream())
+    return out
+
+
 def cheb_filter_noalloc(H: BsrMatrix, X: torch.Tensor, m: int, a: float, b: float, a0: float,
                         out: torch.Tensor) -> torch.Tensor:
     """ttdft_cheb_filter_noalloc: the filter with the library's fixed device
@@ -291,22 +310,39 @@ def cheb_filter_autograd(H: BsrMatrix, X: torch.Tensor, m: int, a: float, b: flo
     return ChebFilter.apply(H.vals, X, H, m, a, b, a0, ckpt_every)
 
 
-def bsr_astype(H: BsrMatrix, dtype: torch.dtype) -> BsrMatrix:
+def _slots_16x32(slot16x4: np.ndarray, per_tile: int) -> np.ndarray:
+    """Positions of entries given in the 16x4 fragment order of FP64/FP32 tiles,
+    in the 16x32 fragment order of BF16 tiles (per_tile values per stored tile;
+    the layouts are documented with ttdft_bsr.vals)."""
+    t, p = np.divmod(np.asarray(slot16x4, dtype=np.int64), 4096)
+    f, q = np.divmod(p, 64)
+    i = 16 * (f & 3) + (q & 15)
+    j = 4 * (f >> 2) + (q >> 4)
+    pos = 512 * (4 * (j >> 5) + (i >> 4)) + 8 * ((i & 15) + 16 * ((j & 31) >> 3)) + (j & 7)
+    return t * per_tile + pos
+
+
+def bsr_astype(H: BsrMatrix, dtype) -> BsrMatrix:
     """The same blocked matrix with its tile values converted on the device by
-    ttdft_cast (round to nearest even); pattern arrays are shared."""
+    ttdft_convert_tiles (round to nearest even; BF16 and bf16x3 tiles in their
+    16x32 fragment order); pattern arrays are shared."""
     code = DTYPE_CODES[dtype]
     if code == H.dtype:
         return H
+    if H.dtype not in (F64, F32):
+        raise ValueError("tile values are converted from FP64 or FP32 tiles")
     slot = H.entry_slot
     if code == BF16_SPLIT:
-        if H.dtype != F64:
-            raise ValueError("the bf16x3 split is made from FP64 tile values")
         vals = torch.empty((H.n_tiles, 8192), dtype=torch.bfloat16, device=H.vals.device)
-        _lib.call("ttdft_split_bf16", _ptr(H.vals), H.n_tiles, _ptr(vals), _stream())
-        slot = (slot // 4096) * 8192 + slot % 4096          # position of the hi value
+        slot = _slots_16x32(slot, 8192)                     # position of the hi value
+    elif code == BF16:
+        vals = torch.empty((H.n_tiles, 4096), dtype=torch.bfloat16, device=H.vals.device)
+        slot = _slots_16x32(slot, 4096)
+    elif code == F32:
+        vals = torch.empty((H.n_tiles, 4096), dtype=torch.float32, device=H.vals.device)
     else:
-        flat = H.vals.reshape(H.n_tiles * 64, 64)  # elementwise: the layout is the same for every dtype
-        vals = cast(flat, dtype).reshape(H.n_tiles, 4096)
+        raise ValueError("tile values convert to FP32, BF16 or bf16x3")
+    _lib.call("ttdft_convert_tiles", _ptr(H.vals), H.dtype, H.n_tiles, _ptr(vals), code, _stream())
     return BsrMatrix(r=H.r, N=H.N, n_block_rows=H.n_block_rows, n_tiles=H.n_tiles,
                      tile_rowptr=H.tile_rowptr, tile_col=H.tile_col, vals=vals, perm=H.perm,
                      inv_perm=H.inv_perm, entry_slot=slot, mask=H.mask, dtype=code,

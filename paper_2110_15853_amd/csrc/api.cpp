@@ -105,13 +105,38 @@ uint16_t f32_to_bf16_rne(float f) {
 // neighbouring block's tile are empty than with plain k-fastest order: 1200
 // instead of 1296 non-empty fragments per block row at h = 4, 768 instead of
 // 840 at h = 3.
+// The blocks themselves are numbered by 2x2x2 patches: every complete patch
+// takes 8 consecutive numbers (its blocks in (i, j, k) order), patches in
+// lexicographic order; the blocks of incomplete patches (the far faces when the
+// block count per axis is odd) follow.  Eight consecutive block rows are then
+// one patch, whose stencils reach a 4x4x4 set of blocks (h <= 4) instead of
+// 8 x 27, so a work-group owning a patch loads each neighbouring panel once for
+// up to 8 of its rows; four consecutive block rows are a 2x2 square in (j, k).
 struct Lattice {
   int64_t r, nb;
-  explicit Lattice(int64_t r_) : r(r_), nb((r_ + 3) / 4) {}
+  std::vector<int64_t> number;   // block (bi*nb + bj)*nb + bk -> block number
+  explicit Lattice(int64_t r_) : r(r_), nb((r_ + 3) / 4), number(nb * nb * nb, -1) {
+    const int64_t np = (nb + 1) / 2;
+    int64_t next = 0;
+    auto place = [&](bool complete) {
+      for (int64_t pi = 0; pi < np; ++pi)
+        for (int64_t pj = 0; pj < np; ++pj)
+          for (int64_t pk = 0; pk < np; ++pk) {
+            const bool full = 2 * pi + 1 < nb && 2 * pj + 1 < nb && 2 * pk + 1 < nb;
+            if (full != complete) continue;
+            for (int64_t d = 0; d < 8; ++d) {
+              const int64_t bi = 2 * pi + (d >> 2), bj = 2 * pj + ((d >> 1) & 1), bk = 2 * pk + (d & 1);
+              if (bi < nb && bj < nb && bk < nb) number[(bi * nb + bj) * nb + bk] = next++;
+            }
+          }
+    };
+    place(true);
+    place(false);
+  }
   int64_t n_block_rows() const { return nb * nb * nb; }
   void split(int64_t I, int64_t &blk, int64_t &loc) const {
     const int64_t i = I / (r * r), j = (I / r) % r, k = I % r;
-    blk = ((i / 4) * nb + j / 4) * nb + k / 4;
+    blk = number[((i / 4) * nb + j / 4) * nb + k / 4];
     const int64_t box = ((i % 4) >> 1) * 2 + ((j % 4) >> 1);   // 2x2x4 box of the block
     const int64_t line = (i & 1) * 2 + (j & 1);                 // k-line inside the box
     loc = (box * 4 + line) * 4 + k % 4;
@@ -267,8 +292,8 @@ ttdft_status ttdft_bsr_build(int32_t r, const int64_t *rowptr, const int32_t *co
       L.split(col[p], bc, lc);
       const int32_t *first = tile_col + tptr[b], *last = tile_col + tptr[b + 1];
       const int64_t t = tptr[b] + (std::lower_bound(first, last, (int32_t)bc) - first);
-      // fragment order: the 16x4 fragment (lc/4, l/16) is 64 consecutive values
-      const int64_t pos = 64 * (4 * (lc >> 2) + (l >> 4)) + 16 * (lc & 3) + (l & 15);
+      // fragment order of the tile type (16x4 for F64 / F32, 16x32 for BF16)
+      const int64_t pos = tile_pos(dtype, (int)l, (int)lc);
       const int64_t slot = (dtype == TTDFT_BF16_SPLIT ? 2 : 1) * t * kTileElems + pos;
       if (dtype == TTDFT_F64) {
         ((double *)vals)[slot] = val[p];
@@ -358,6 +383,14 @@ ttdft_status filter_check(const ttdft_bsr *H, const void *X, int64_t ldx, const 
 ttdft_status filter_enqueue(const ttdft_bsr &H, const void *X, int64_t ldx, void *Y, int64_t ldy,
                             int64_t n_vec, int32_t m, double a, double b, double a0,
                             ttdft_dtype x_dtype, void *work, hipStream_t s) {
+  return filter_enqueue_schedule(H, H, 0, X, ldx, Y, ldy, n_vec, m, a, b, a0, x_dtype, work, s);
+}
+
+// steps k < m - m_late take their product with H_early, the others with H_late
+ttdft_status filter_enqueue_schedule(const ttdft_bsr &H_early, const ttdft_bsr &H_late, int32_t m_late,
+                                     const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t n_vec,
+                                     int32_t m, double a, double b, double a0, ttdft_dtype x_dtype,
+                                     void *work, hipStream_t s) {
   // coefficient schedule of Algorithm 1 (Sec. 3.4), FP64 on the host
   std::vector<double> alpha(m), beta(m);
   double c;
@@ -371,6 +404,7 @@ ttdft_status filter_enqueue(const ttdft_bsr &H, const void *X, int64_t ldx, void
     const int64_t ldc = k == 0 ? ldx : ld_of(k);
     const void *prev = k == 0 ? nullptr : (k == 1 ? X : buf(k - 1));
     const int64_t ldp = k == 0 ? 0 : (k == 1 ? ldx : ld_of(k - 1));
+    const ttdft_bsr &H = k < m - m_late ? H_early : H_late;
     hipError_t err = launch_cheb_step(H, cur, ldc, prev, ldp, buf(k + 1), ld_of(k + 1), n_vec,
                                       alpha[k], c, beta[k], x_dtype, s);
     if (err != hipSuccess) return hip_status(err, "cheb_filter step");
@@ -397,6 +431,34 @@ ttdft_status ttdft_cheb_filter(const ttdft_bsr *H, const void *X, int64_t ldx, v
   if (overlap(sw, span_of(Y, rows, ldy, n_vec, elt)) || overlap(sw, span_of(X, rows, ldx, n_vec, elt)))
     return fail(TTDFT_ERR_ALIAS, "workspace overlaps X or Y");
   return filter_enqueue(*H, X, ldx, Y, ldy, n_vec, m, a, b, a0, x_dtype, work, (hipStream_t)stream);
+}
+
+ttdft_status ttdft_cheb_filter_schedule(const ttdft_bsr *H_early, const ttdft_bsr *H_late,
+                                        int32_t m_late, const void *X, int64_t ldx, void *Y,
+                                        int64_t ldy, int64_t n_vec, int32_t m, double a, double b,
+                                        double a0, ttdft_dtype x_dtype, void *work,
+                                        size_t work_bytes, void *stream) {
+  ttdft_status st = filter_check(H_early, X, ldx, Y, ldy, n_vec, m, a, b, a0, x_dtype);
+  if (st != TTDFT_OK) return st;
+  st = filter_check(H_late, X, ldx, Y, ldy, n_vec, m, a, b, a0, x_dtype);
+  if (st != TTDFT_OK) return st;
+  if (H_early->n_block_rows != H_late->n_block_rows || H_early->n_tiles != H_late->n_tiles)
+    return fail(TTDFT_ERR_SHAPE, "H_early and H_late must be the same blocked matrix "
+                                 "(%lld/%lld block rows, %lld/%lld tiles)",
+                (long long)H_early->n_block_rows, (long long)H_late->n_block_rows,
+                (long long)H_early->n_tiles, (long long)H_late->n_tiles);
+  if (m_late < 0 || m_late > m)
+    return fail(TTDFT_ERR_DEGREE, "m_late = %d outside 0 .. m = %d", m_late, m);
+  const int64_t rows = H_early->n_block_rows * 64;
+  const size_t elt = dtype_size(x_dtype);
+  const size_t need = ttdft_cheb_filter_workspace(H_early, n_vec, x_dtype);
+  if (m >= 2 && (!work || work_bytes < need))
+    return fail(TTDFT_ERR_WORKSPACE, "workspace of %zu bytes needed", need);
+  const Span sw = m >= 2 ? span_bytes(work, need) : Span{};
+  if (overlap(sw, span_of(Y, rows, ldy, n_vec, elt)) || overlap(sw, span_of(X, rows, ldx, n_vec, elt)))
+    return fail(TTDFT_ERR_ALIAS, "workspace overlaps X or Y");
+  return filter_enqueue_schedule(*H_early, *H_late, m_late, X, ldx, Y, ldy, n_vec, m, a, b, a0,
+                                 x_dtype, work, (hipStream_t)stream);
 }
 
 size_t ttdft_check_finite_workspace(void) { return 16; }
@@ -450,6 +512,22 @@ ttdft_status ttdft_split_bf16(const double *src, int64_t n_tiles, void *dst, voi
   if (overlap(span_bytes(src, (size_t)n_tiles * kTileElems * 8), span_bytes(dst, (size_t)n_tiles * kTileElems * 4)))
     return fail(TTDFT_ERR_ALIAS, "src and dst overlap");
   return hip_status(launch_split_bf16(src, n_tiles, dst, (hipStream_t)stream), "split launch");
+}
+
+ttdft_status ttdft_convert_tiles(const void *src, ttdft_dtype src_dtype, int64_t n_tiles, void *dst,
+                                 ttdft_dtype dst_dtype, void *stream) {
+  if (!src || !dst) return fail(TTDFT_ERR_NULL, "src or dst is NULL");
+  if (n_tiles < 0) return fail(TTDFT_ERR_SHAPE, "n_tiles = %lld", (long long)n_tiles);
+  if (!(src_dtype == TTDFT_F64 || src_dtype == TTDFT_F32) ||
+      !(dst_dtype == TTDFT_F32 || dst_dtype == TTDFT_BF16 || dst_dtype == TTDFT_BF16_SPLIT) ||
+      src_dtype == dst_dtype)
+    return fail(TTDFT_ERR_DTYPE, "tile conversion %d -> %d not supported", (int)src_dtype, (int)dst_dtype);
+  const size_t nb_src = (size_t)n_tiles * kTileElems * dtype_size(src_dtype);
+  const size_t nb_dst = (size_t)n_tiles * kTileElems * tile_value_bytes(dst_dtype);
+  if (overlap(span_bytes(src, nb_src), span_bytes(dst, nb_dst)))
+    return fail(TTDFT_ERR_ALIAS, "src and dst overlap");
+  return hip_status(launch_convert_tiles(src, src_dtype, n_tiles, dst, dst_dtype, (hipStream_t)stream),
+                    "convert_tiles launch");
 }
 
 ttdft_status ttdft_gather_rows(const void *src, int64_t lds, int64_t rows_src, void *dst,

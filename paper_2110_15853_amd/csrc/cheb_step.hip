@@ -53,10 +53,12 @@ template <> struct Mfma4<float> {
 constexpr int F64_NV = 128, F64_THREADS = 512;
 // launch order: column groups of ORDER_CGROUP tiles outermost; each XCD takes runs
 // of ORDER_CHUNK consecutive block rows (all column tiles of the group), the 8
-// XCDs working on neighbouring runs at the same time.  Runs of 4 block rows let
-// the rows resident on one XCD share more of their neighbours' Y_k panels in L2
-// (measured 3% faster than runs of 1; 8 and longer were slower again).
-constexpr int ORDER_CGROUP = 16, ORDER_CHUNK = 4;
+// XCDs working on neighbouring runs at the same time.  A run of 8 block rows is
+// one 2x2x2 patch of lattice blocks in the builder's numbering, whose rows
+// share most of their neighbours' Y_k panels in L2 (FP64: 15.7 ms per step at
+// the full-size workload, against 16.6 ms for runs of 4 and 17.5 ms for runs
+// of 2).
+constexpr int ORDER_CGROUP = 16, ORDER_CHUNK = 8;
 
 __device__ inline int64_t group_order(int64_t g, int64_t G, int64_t C) {
   // hardware ids go round-robin over 8 XCDs; give each XCD C consecutive logical
@@ -249,159 +251,332 @@ template <> __device__ inline float to_f32<__bf16>(__bf16 v) { return (float)v; 
 template <typename TX> __device__ inline TX from_f32(float v);
 template <> __device__ inline float from_f32<float>(float v) { return v; }
 template <> __device__ inline __bf16 from_f32<__bf16>(float v) { return (__bf16)v; }
+template <> __device__ inline __bf16 buffer_load<__bf16>(__amdgpu_buffer_rsrc_t rs, int32_t voff, int32_t soff) {
+  return __builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(rs, voff, soff, 0));
+}
 
-// Pipelined BF16 path: BF16 H tiles, FP32 or BF16 iterates, FP32 accumulation
-// on the 16x16x32 bf16 op.  Same decomposition as cheb_step_mfma (8 waves,
-// 128 vectors, wave w owns vectors 16w .. 16w+15):
-//  - A (H tile, 8 KB): double-buffered in LDS in the 16x32 fragment order of
-//    the bf16 op, lane l of fragment (kk, mb) holding H[16mb + (l&15)][32kk +
-//    8(l>>4) .. +7] as one 16-byte read; each thread loads 16 bytes of the tile
-//    (8 rows of one column in the stored 16x4 fragment order) and scatters them;
-//  - B (Y_k): lane l gathers Y_k[32kk + 8(l>>4) + t][col], t = 0..7, rounds to
-//    bf16 and packs them; the next tile's values are fetched during the current
-//    tile's contraction.
-//  - a 16x32 fragment is skipped when all eight 16x4 sub-blocks it covers are
-//    clear in the fragment mask.
-//  - SPLIT (BF16_SPLIT tiles, FP32 iterates): the tile holds hi and lo bf16
-//    parts, each iterate value y is split into hi = bf16(y), lo = bf16(y - hi),
-//    and every fragment takes the three products hi*hi + hi*lo + lo*hi (the
-//    lo*lo term, 2^-16 relative, is dropped).
+// ---------------------------------------------------------------------------
+// BF16 step kernel over patches of block rows: BF16 tiles (or hi + lo pairs),
+// FP32 or BF16 iterates, FP32 accumulation on the 16x16x32 bf16 op.
+//
+// A work-group owns PB_R = 8 consecutive block rows (one 2x2x2 patch of
+// lattice blocks in the builder's numbering) and 128 vectors; wave w owns
+// vectors 16w .. 16w+15, lane l the vector 16w + l%16 and the rows
+// 8(l/16) .. +7 of each 32-row half of a panel.  The patch rows' tiles are
+// walked in the order of their block column: the union of the rows' tile
+// columns (4x4x4 = 64 blocks for a patch at h <= 4, against 8 x 27 tiles) is
+// built in LDS at the start, and each neighbouring Y_k panel is read once per
+// union step and contracted with every patch row's tile in that block column.
+// The BF16 step is bound by bytes, and the panels (not the 4x smaller tiles)
+// are most of them: this cuts the panel reads by 27*8/64.
+//  - A (H tiles, 16x32 fragment order) moved to LDS by LDS-DMA through a ring
+//    of HS stages, one tile per step, HS - 1 tiles ahead;
+//  - B (Y_k panel): FP32 iterates moved to LDS by buffer LDS-DMA (range-checked
+//    against the panel) through a ring of 2 stages, two union steps ahead (a
+//    stage is free again once every lane has read its 8 rows of its vector and
+//    rounded them to bf16 at the start of its step; SPLIT: hi = bf16(y),
+//    lo = bf16(y - hi)); rows padded so the reads hit 64 distinct banks; BF16
+//    iterates are read into registers by buffer loads one union step ahead;
+//  - completion of each wave's transfers is tracked by counting the memory
+//    instructions it issued after the one waited for (rings of issue counts
+//    in LDS) and waited for with s_waitcnt (a jump over the possible counts)
+//    before a barrier;
+//  - every 16x32 fragment of a tile is contracted: skipping the empty ones
+//    (16% at h = 4) saves matrix-core work, which is not what bounds this step,
+//    and costs a scalar test per fragment;
+//  - SPLIT: three products hi*hi + hi*lo + lo*hi per fragment.
+// Patches with more than PB_CAP tiles (not produced by stencils with h <= 4) are
+// walked one block row at a time in chunks of PB_CAP tiles.
+constexpr int PB_R = 8, PB_WAVES = 8, PB_THREADS = 64 * PB_WAVES, PB_NV = 16 * PB_WAVES;
+constexpr int PB_CAP = 27 * PB_R;
+constexpr int PB_YS = 2;                 // Y panel ring stages
+constexpr int PB_YCH = 1024 + 16;        // bytes per two-row chunk of an FP32 panel in LDS
+
+// wait until at most k <= n of this wave's memory instructions are outstanding
+// (n wave-uniform; a jump to the matching immediate)
+__device__ inline void wait_vmcnt_le(int n) {
+  switch (n < 0 ? 0 : (n > 40 ? 40 : n)) {
+#define TTDFT_WAIT_CASE(k) case k: wait_vmcnt<k>(); break;
+    TTDFT_WAIT_CASE(0) TTDFT_WAIT_CASE(1) TTDFT_WAIT_CASE(2) TTDFT_WAIT_CASE(3) TTDFT_WAIT_CASE(4)
+    TTDFT_WAIT_CASE(5) TTDFT_WAIT_CASE(6) TTDFT_WAIT_CASE(7) TTDFT_WAIT_CASE(8) TTDFT_WAIT_CASE(9)
+    TTDFT_WAIT_CASE(10) TTDFT_WAIT_CASE(11) TTDFT_WAIT_CASE(12) TTDFT_WAIT_CASE(13) TTDFT_WAIT_CASE(14)
+    TTDFT_WAIT_CASE(15) TTDFT_WAIT_CASE(16) TTDFT_WAIT_CASE(17) TTDFT_WAIT_CASE(18) TTDFT_WAIT_CASE(19)
+    TTDFT_WAIT_CASE(20) TTDFT_WAIT_CASE(21) TTDFT_WAIT_CASE(22) TTDFT_WAIT_CASE(23) TTDFT_WAIT_CASE(24)
+    TTDFT_WAIT_CASE(25) TTDFT_WAIT_CASE(26) TTDFT_WAIT_CASE(27) TTDFT_WAIT_CASE(28) TTDFT_WAIT_CASE(29)
+    TTDFT_WAIT_CASE(30) TTDFT_WAIT_CASE(31) TTDFT_WAIT_CASE(32) TTDFT_WAIT_CASE(33) TTDFT_WAIT_CASE(34)
+    TTDFT_WAIT_CASE(35) TTDFT_WAIT_CASE(36) TTDFT_WAIT_CASE(37) TTDFT_WAIT_CASE(38) TTDFT_WAIT_CASE(39)
+    TTDFT_WAIT_CASE(40)
+#undef TTDFT_WAIT_CASE
+    default: wait_vmcnt<0>();
+  }
+}
+
 template <typename TX, bool SPLIT>
-__global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_bf16_pipe(
+__global__ __launch_bounds__(PB_THREADS, 1) void cheb_step_bf16_patch(
     const int32_t *__restrict__ rowptr, const int32_t *__restrict__ tcol,
     const __bf16 *__restrict__ vals, const TX *__restrict__ Yk, int64_t ldk,
     const TX *__restrict__ Yp, int64_t ldp, TX *Yo, int64_t ldo, int64_t n_vec, int64_t n_ct,
-    int64_t n_block_rows, int64_t cgroup, int64_t n_wg, float alpha, float c, float beta,
-    const uint64_t *__restrict__ frag_mask) {
+    int64_t n_block_rows, int64_t cgroup, int64_t n_wg, float alpha, float c, float beta) {
+  constexpr bool YDMA = sizeof(TX) == 4;
   constexpr int PARTS = SPLIT ? 2 : 1;
+  constexpr int TILE_VALS = 4096 * PARTS;                  // bf16 values per stored tile
+  constexpr int XFER = TILE_VALS * 2 / (PB_THREADS * 16);  // 16-byte H transfers per lane per tile
+  constexpr int YX = 32 / PB_WAVES;                        // two-row Y transfers per wave per panel
+  constexpr int HS = SPLIT ? 4 : 8;                        // H ring stages
   static_assert(!SPLIT || sizeof(TX) == 4, "split products need FP32 iterates");
-  // [buf][part][kk][mb][lane][8]
-  __shared__ __attribute__((aligned(16))) __bf16 sH[2][PARTS * 2 * 4 * 64 * 8];
-  const int64_t L = group_order(blockIdx.x, n_wg, cgroup * ORDER_CHUNK);
-  const int64_t per_group = n_block_rows * cgroup;
+  __shared__ __attribute__((aligned(16))) __bf16 sH[HS][TILE_VALS];
+  __shared__ __attribute__((aligned(16))) char sY[YDMA ? PB_YS * 32 * PB_YCH : 16];
+  __shared__ int s_val[PB_CAP], s_row[PB_CAP], s_first[PB_CAP], s_ucol[PB_CAP], s_seq[PB_CAP];
+  __shared__ int s_ut[PB_CAP][PB_R];
+  __shared__ int s_rp[PB_R + 1];
+  __shared__ int s_recH[PB_WAVES][HS], s_recY[PB_WAVES][PB_YS];
+
+  const int64_t n_patch = (n_block_rows + PB_R - 1) / PB_R;
+  const int64_t L = group_order(blockIdx.x, n_wg, cgroup);
+  const int64_t per_group = n_patch * cgroup;
   const int64_t cg = L / per_group, rem = L % per_group;
-  const int64_t B = rem / cgroup;
+  const int64_t B0 = (rem / cgroup) * PB_R;
   const int64_t ct = cg * cgroup + rem % cgroup;
   if (ct >= n_ct) return;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t col = ct * F64_NV + 16 * w + (lane & 15);
-  // columns past n_vec load a clamped in-range column (never stored; an output
+  const int nrows = (int)min<int64_t>(PB_R, n_block_rows - B0);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4;
+  const int64_t col = ct * PB_NV + 16 * w + (lane & 15);
+  // a column past n_vec reads a clamped, in-range column (never stored; an output
   // column depends only on its own B column), so every load is unconditional
   const int64_t colc = min(col, n_vec - 1);
-  const int kgrp = lane >> 4;
 
-  v4f acc[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = v4f{0, 0, 0, 0};
-  const int t_begin = rowptr[B], t_end = rowptr[B + 1];
+  if (tid <= nrows) s_rp[tid] = rowptr[B0 + tid];
 
-  // H staging: thread tid moves 8 consecutive stored bf16 (16 bytes) per part
-  v8bf hreg[PARTS];
-  auto load_h = [&](int t) {
+  v4f acc[PB_R][4];
 #pragma unroll
-    for (int pt = 0; pt < PARTS; ++pt)
-      hreg[pt] = *reinterpret_cast<const v8bf *>(vals + (int64_t)t * PARTS * kTileElems +
-                                                 pt * kTileElems + 8 * tid);
-  };
-  auto store_h = [&](int buf) {
-    // thread tid holds stored values 8 tid .. 8 tid + 7: fragment f = tid / 8 of
-    // the 16x4 order, its lanes fl0 .. fl0 + 7, i.e. rows i0 .. i0 + 7 of column j
-    const int f = tid >> 3, fl0 = (tid & 7) * 8;
-    const int i0 = 16 * (f & 3) + (fl0 & 15), j = 4 * (f >> 2) + (fl0 >> 4);
-    const int kk = j >> 5, g = (j & 31) >> 3, e = j & 7, mb = i0 >> 4;
+  for (int i = 0; i < PB_R; ++i)
 #pragma unroll
-    for (int pt = 0; pt < PARTS; ++pt) {
-      __bf16 *dst = &sH[buf][pt * kTileElems + ((kk * 4 + mb) * 64 + (i0 & 15) + 16 * g) * 8 + e];
+    for (int mb = 0; mb < 4; ++mb) acc[i][mb] = v4f{0, 0, 0, 0};
+
+  const int32_t panel_bytes = (int32_t)(64 * ldk * (int64_t)sizeof(TX));
+  // memory instructions this wave has issued for the two rings (wave-uniform)
+  int nH = 0, nY = 0;
+
+  // ---- H tile t into ring stage st (16 bytes per lane, fragment order kept)
+  auto dma_h = [&](int t, int st) {
+    const __bf16 *src = vals + (int64_t)t * TILE_VALS + (w * XFER) * 512 + 8 * lane;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) dst[8 * u] = hreg[pt][u];
+    for (int q = 0; q < XFER; ++q) {
+      const uint32_t lds = (uint32_t)(uintptr_t)(lds_void_t *)(&sH[st][(w * XFER + q) * 512]);
+      asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                   :
+                   : "s"(__builtin_amdgcn_readfirstlane(lds)), "v"(src + q * 512)
+                   : "memory", "m0");
     }
   };
-  // two register sets for the Y_k values: one being contracted, one being fetched
-  TX bA[2][8], bB[2][8];
-  auto load_b = [&](int t, TX (&dst)[2][8]) {
-    const TX *Xp = Yk + (int64_t)tcol[t] * 64 * ldk + colc;
+  // ---- FP32 Y panel of block column Bc into ring stage st: two rows per wave
+  // transfer (lanes 0-31 row 2ch, lanes 32-63 row 2ch+1, 4 vectors per lane),
+  // chunk ch at st*32*PB_YCH + ch*PB_YCH; offsets past the panel read 0
+  const int32_t yvoff = (int32_t)((((int64_t)(lane >> 5) + 2 * w) * ldk + ct * PB_NV + 4 * (lane & 31)) *
+                                  (int64_t)sizeof(TX));
+  auto dma_y = [&](int64_t Bc, int st) {
+    if constexpr (YDMA) {
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)(Yk + Bc * 64 * ldk), 0, panel_bytes, kBufferWord3);
+#pragma unroll
+      for (int q = 0; q < YX; ++q) {
+        const int ch = PB_WAVES * q + w;
+        const uint32_t lds = (uint32_t)(uintptr_t)(lds_void_t *)(&sY[st * 32 * PB_YCH + ch * PB_YCH]);
+        const int32_t so = (int32_t)(2 * PB_WAVES * q * ldk * (int64_t)sizeof(TX));
+        asm volatile("s_mov_b32 m0, %0\n\tbuffer_load_dwordx4 %1, %2, %3 offen lds"
+                     :
+                     : "s"(__builtin_amdgcn_readfirstlane(lds)), "v"(yvoff), "s"(rs), "s"(so)
+                     : "memory", "m0");
+      }
+    }
+  };
+  // BF16 iterates: the lane's values straight into registers
+  const int32_t voff = (int32_t)(((int64_t)8 * g * ldk + colc) * (int64_t)sizeof(TX));
+  TX yr[2][8];
+  auto load_y_regs = [&](int64_t Bc) {
+    if constexpr (!YDMA) {
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)(Yk + Bc * 64 * ldk), 0, panel_bytes, kBufferWord3);
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          yr[kk][t] = buffer_load<TX>(rs, voff, (int32_t)((32 * kk + t) * ldk * (int64_t)sizeof(TX)));
+    }
+  };
+  v8bf bh[2], bl[2];   // [kk]
+  auto convert_y = [&](int st) {
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int kr = 32 * kk + 8 * kgrp + q;
-        dst[kk][q] = Xp[(int64_t)kr * ldk];
+      for (int t = 0; t < 8; ++t) {
+        float v;
+        if constexpr (YDMA) {
+          const int r = 32 * kk + 8 * g + t;
+          v = *reinterpret_cast<const float *>(
+              &sY[st * 32 * PB_YCH + (r >> 1) * PB_YCH + (r & 1) * 512 + 4 * (16 * w + (lane & 15))]);
+        } else {
+          v = to_f32<TX>(yr[kk][t]);
+        }
+        bh[kk][t] = (__bf16)v;
+        if (SPLIT) bl[kk][t] = (__bf16)(v - (float)bh[kk][t]);
       }
   };
-  // sub-blocks 4*kk4 + mb, kk4 = 8kk .. 8kk+7, sit at bits 32kk + 4j + mb
-  auto mma_tile = [&](int buf, uint64_t fm, const TX (&src)[2][8]) {
+  // all A fragments of the tile are read from LDS before the matrix-core ops,
+  // so the LDS latency is paid once per tile, not once per op
+  auto mma_tile = [&](v4f (&ac)[4], const __bf16 *sA) {
+    v8bf a[8], alo[SPLIT ? 8 : 1];
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-      v8bf b, blo;
+    for (int f = 0; f < 8; ++f) {
+      a[f] = *reinterpret_cast<const v8bf *>(sA + f * 512 + 8 * lane);
+      if (SPLIT) alo[f] = *reinterpret_cast<const v8bf *>(sA + 4096 + f * 512 + 8 * lane);
+    }
+    __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the ops
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const float y = to_f32<TX>(src[kk][q]);
-        b[q] = (__bf16)y;
-        if (SPLIT) blo[q] = (__bf16)(y - (float)b[q]);
-      }
+    for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb) {
-        if (((fm >> (32 * kk + mb)) & 0x11111111ull) == 0) continue;
-        const v8bf a = *reinterpret_cast<const v8bf *>(&sH[buf][((kk * 4 + mb) * 64 + lane) * 8]);
-        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[mb], 0, 0, 0);
+        const int f = 4 * kk + mb;
+        ac[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f], bh[kk], ac[mb], 0, 0, 0);
         if (SPLIT) {
-          const v8bf alo = *reinterpret_cast<const v8bf *>(
-              &sH[buf][kTileElems + ((kk * 4 + mb) * 64 + lane) * 8]);
-          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, blo, acc[mb], 0, 0, 0);
-          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, b, acc[mb], 0, 0, 0);
+          ac[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f], bl[kk], ac[mb], 0, 0, 0);
+          ac[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[f], bh[kk], ac[mb], 0, 0, 0);
         }
       }
+  };
+  // issue helpers that record, per ring slot, the other ring's count at issue
+  auto issue_h = [&](int p) {
+    dma_h(__builtin_amdgcn_readfirstlane(s_seq[p]), p % HS);
+    s_recH[w][p % HS] = nY;
+    ++nH;
+  };
+  auto issue_y = [&](int u) {
+    const int64_t Bc = __builtin_amdgcn_readfirstlane(s_ucol[u]);
+    if constexpr (YDMA) {
+      dma_y(Bc, u % PB_YS);
+      s_recY[w][u % PB_YS] = nH;
+      ++nY;
+    } else {
+      load_y_regs(Bc);
     }
   };
-  // the last tile fetches itself again as "next": no load is conditional
-  auto step = [&](int t, int buf, const TX (&cur)[2][8], TX (&nxt)[2][8]) {
-    const int tn = min(t + 1, t_end - 1);
-    const uint64_t fm = frag_mask ? frag_mask[t] : ~0ull;
-    load_h(tn);
-    load_b(tn, nxt);
-    mma_tile(buf, fm, cur);
-    store_h(buf ^ 1);
-    __syncthreads();
-  };
 
-  if (t_begin < t_end) {
-    load_h(t_begin);
-    load_b(t_begin, bA);
-    store_h(0);
-    __syncthreads();
-  }
-  for (int t = t_begin; t < t_end; t += 2) {
-    step(t, 0, bA, bB);
-    if (t + 1 < t_end) step(t + 1, 1, bB, bA);
+  __syncthreads();
+  const int e_all0 = s_rp[0], e_all1 = s_rp[nrows];
+  const bool one_segment = e_all1 - e_all0 <= PB_CAP;
+  // segments: the whole patch, or (rare) each block row in chunks of PB_CAP tiles
+  const int n_seg_rows = one_segment ? 1 : nrows;
+  for (int sr = 0; sr < n_seg_rows; ++sr) {
+    const int r0 = one_segment ? e_all0 : s_rp[sr], r1 = one_segment ? e_all1 : s_rp[sr + 1];
+    for (int e_begin = r0; e_begin < r1; e_begin += PB_CAP) {
+      const int ne = min(PB_CAP, r1 - e_begin);
+      // ---- union schedule of this segment (LDS): distinct block columns in
+      // ascending order (union steps u), per step the tile of each patch row,
+      // and the tile sequence in (u, row) order
+      for (int e = tid; e < ne; e += PB_THREADS) {
+        const int tt = e_begin + e;
+        s_val[e] = tcol[tt];
+        int i = 0;
+        while (i + 1 < nrows && s_rp[i + 1] <= tt) ++i;
+        s_row[e] = i;
+#pragma unroll
+        for (int r = 0; r < PB_R; ++r) s_ut[e][r] = -1;
+      }
+      __syncthreads();
+      for (int e = tid; e < ne; e += PB_THREADS) {
+        const int v = s_val[e];
+        int first = 1;
+        for (int e2 = 0; e2 < e; ++e2) first &= (s_val[e2] != v);
+        s_first[e] = first;
+      }
+      __syncthreads();
+      for (int e = tid; e < ne; e += PB_THREADS) {
+        const int v = s_val[e], i = s_row[e];
+        int u = 0, pos = 0;
+        for (int e2 = 0; e2 < ne; ++e2) {
+          const int v2 = s_val[e2];
+          u += (s_first[e2] && v2 < v);
+          pos += (v2 < v || (v2 == v && s_row[e2] < i));
+        }
+        s_ut[u][i] = e_begin + e;
+        if (s_first[e]) s_ucol[u] = v;
+        s_seq[pos] = e_begin + e;
+      }
+      __syncthreads();
+      int nu = 0;
+      for (int e = 0; e < ne; ++e) nu += s_first[e];
+
+      // ---- pipeline: H tiles HS - 1 ahead in sequence order, the Y_k panel
+      // two union steps ahead
+      nH = 0;
+      nY = 0;
+      for (int p = 0; p < HS - 1 && p < ne; ++p) issue_h(p);
+      if (nu > 0) issue_y(0);
+      if (YDMA && nu > 1) issue_y(1);
+      int pos = 0;
+      for (int u = 0; u < nu; ++u) {
+        if constexpr (YDMA) {
+          // this wave's transfers of panel u are done when at most the memory
+          // instructions issued after them are outstanding
+          wait_vmcnt_le(YX * (nY - 1 - u) + XFER * (nH - s_recY[w][u % PB_YS]));
+          __syncthreads();               // every wave's part of panel u is in LDS
+          convert_y(u % PB_YS);
+          __syncthreads();               // every wave has its copy: the stage takes panel u + 2
+          if (u + 2 < nu) issue_y(u + 2);
+        } else {
+          convert_y(0);
+          if (u + 1 < nu) issue_y(u + 1);
+        }
+#pragma unroll
+        for (int i = 0; i < PB_R; ++i) {
+          const int t = __builtin_amdgcn_readfirstlane(s_ut[u][i]);
+          if (t < 0) continue;
+          // tile `pos`: done when at most the instructions issued after it are outstanding
+          wait_vmcnt_le(XFER * (nH - 1 - pos) + YX * (nY - s_recH[w][pos % HS]));
+          __syncthreads();               // every wave's part is in LDS; stage pos-1 is free
+          if (pos + HS - 1 < ne) issue_h(pos + HS - 1);
+          mma_tile(acc[i], sH[pos % HS]);
+          ++pos;
+        }
+      }
+      __syncthreads();   // the schedule arrays are rebuilt by the next segment
+    }
   }
 
-  // epilogue: loads first, then the stores
-  float yk[4][4], yp[4][4];
+  // epilogue per block row of the patch: loads first, then the stores
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      yk[mb][q] = to_f32<TX>(Yk[(B * 64 + 16 * mb + 4 * (lane >> 4) + q) * ldk + colc]);
-  if (beta != 0.0f) {
+  for (int i = 0; i < PB_R; ++i) {
+    if (i >= nrows) break;
+    const int64_t B = B0 + i;
+    float yk[4][4], yp[4][4];
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        yp[mb][q] = to_f32<TX>(Yp[(B * 64 + 16 * mb + 4 * (lane >> 4) + q) * ldp + colc]);
-  } else {
+        yk[mb][q] = to_f32<TX>(Yk[(B * 64 + 16 * mb + 4 * g + q) * ldk + colc]);
+    if (beta != 0.0f) {
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+      for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) yp[mb][q] = 0.0f;
-  }
-  if (col >= n_vec) return;
+        for (int q = 0; q < 4; ++q)
+          yp[mb][q] = to_f32<TX>(Yp[(B * 64 + 16 * mb + 4 * g + q) * ldp + colc]);
+    } else {
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+      for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t grow = B * 64 + 16 * mb + 4 * (lane >> 4) + q;
-      Yo[grow * ldo + col] = from_f32<TX>(alpha * (acc[mb][q] - c * yk[mb][q]) - beta * yp[mb][q]);
+        for (int q = 0; q < 4; ++q) yp[mb][q] = 0.0f;
     }
+    if (col < n_vec) {
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          Yo[(B * 64 + 16 * mb + 4 * g + q) * ldo + col] =
+              from_f32<TX>(alpha * (acc[i][mb][q] - c * yk[mb][q]) - beta * yp[mb][q]);
+    }
+  }
 }
 
 }  // namespace
@@ -427,27 +602,27 @@ hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, con
                          H.n_block_rows, cgroup, wg, (float)alpha, (float)c, (float)beta,
                          H.frag_mask);
   } else {
-    const int64_t ctp = (n_vec + F64_NV - 1) / F64_NV;
+    const int64_t ctp = (n_vec + PB_NV - 1) / PB_NV;
     const int64_t cgroup = std::min<int64_t>(ctp, ORDER_CGROUP);
     const int64_t n_groups = (ctp + cgroup - 1) / cgroup;
-    const int64_t wg = n_groups * H.n_block_rows * cgroup;
+    const int64_t n_patch = (H.n_block_rows + PB_R - 1) / PB_R;
+    const int64_t wg = n_groups * n_patch * cgroup;
     if (wg > 0x7fffffff) return hipErrorInvalidConfiguration;
     if (H.dtype == TTDFT_BF16_SPLIT)
-      hipLaunchKernelGGL((cheb_step_bf16_pipe<float, true>), dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
+      hipLaunchKernelGGL((cheb_step_bf16_patch<float, true>), dim3((unsigned)wg), dim3(PB_THREADS), 0, s,
                          H.tile_rowptr, H.tile_col, (const __bf16 *)H.vals, (const float *)Yk, ldk,
                          (const float *)Yp, ldp, (float *)Yo, ldo, n_vec, ctp, H.n_block_rows,
-                         cgroup, wg, (float)alpha, (float)c, (float)beta, H.frag_mask);
+                         cgroup, wg, (float)alpha, (float)c, (float)beta);
     else if (xt == TTDFT_F32)
-      hipLaunchKernelGGL((cheb_step_bf16_pipe<float, false>), dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
+      hipLaunchKernelGGL((cheb_step_bf16_patch<float, false>), dim3((unsigned)wg), dim3(PB_THREADS), 0, s,
                          H.tile_rowptr, H.tile_col, (const __bf16 *)H.vals, (const float *)Yk, ldk,
                          (const float *)Yp, ldp, (float *)Yo, ldo, n_vec, ctp, H.n_block_rows,
-                         cgroup, wg, (float)alpha, (float)c, (float)beta, H.frag_mask);
+                         cgroup, wg, (float)alpha, (float)c, (float)beta);
     else
-      hipLaunchKernelGGL((cheb_step_bf16_pipe<__bf16, false>), dim3((unsigned)wg), dim3(F64_THREADS), 0, s,
+      hipLaunchKernelGGL((cheb_step_bf16_patch<__bf16, false>), dim3((unsigned)wg), dim3(PB_THREADS), 0, s,
                          H.tile_rowptr, H.tile_col, (const __bf16 *)H.vals, (const __bf16 *)Yk,
                          ldk, (const __bf16 *)Yp, ldp, (__bf16 *)Yo, ldo, n_vec, ctp,
-                         H.n_block_rows, cgroup, wg, (float)alpha, (float)c, (float)beta,
-                         H.frag_mask);
+                         H.n_block_rows, cgroup, wg, (float)alpha, (float)c, (float)beta);
   }
   return hipGetLastError();
 }

@@ -94,25 +94,54 @@ hipError_t launch_gather_rows(const void *src, int64_t lds, void *dst, int64_t l
 }
 
 namespace {
-// per tile: hi = bf16(fp32(h)), lo = bf16(fp32(h) - hi), the hi block then the lo block
-__global__ void split_bf16_kernel(const double *__restrict__ src, int64_t total, __bf16 *__restrict__ dst) {
+// Tile values from the 16x4 fragment order of FP64 / FP32 tiles to another tile
+// type.  F32 keeps the 16x4 order (a plain rounding).  BF16 and BF16_SPLIT use
+// the 16x32 order of the bf16 op: destination value d of a tile holds entry
+// (i, j) with fragment d/512 = 4*(j/32) + i/16, lane (d/8)%64 = i%16 + 16*((j%32)/8)
+// and j%8 = d%8; it is read from the source position of (i, j).  BF16_SPLIT
+// holds hi = bf16(fp32(h)) in the first 4096 values of a tile and
+// lo = bf16(fp32(h) - hi) in the next 4096 (the subtraction is exact in FP32).
+template <typename S>
+__global__ __launch_bounds__(256) void convert_tiles_kernel(const S *__restrict__ src, int64_t total,
+                                                            void *__restrict__ dst, int dt) {
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-    const int64_t t = e / kTileElems, p = e % kTileElems;
-    float h32 = (float)src[e];
-    asm volatile("" : "+v"(h32));   // two roundings, as bf16_via_f32
+    const int64_t t = e / kTileElems;
+    const int d = (int)(e % kTileElems);
+    if (dt == TTDFT_F32) {
+      ((float *)dst)[e] = (float)src[e];
+      continue;
+    }
+    const int f = d >> 9, L = (d >> 3) & 63;
+    const int i = 16 * (f & 3) + (L & 15), j = 32 * (f >> 2) + 8 * (L >> 4) + (d & 7);
+    float h32 = (float)src[t * kTileElems + tile_pos_16x4(i, j)];
+    asm volatile("" : "+v"(h32));   // two roundings from FP64, as bf16_via_f32
     const __bf16 hi = (__bf16)h32;
-    dst[2 * t * kTileElems + p] = hi;
-    dst[2 * t * kTileElems + kTileElems + p] = (__bf16)(h32 - (float)hi);
+    if (dt == TTDFT_BF16) {
+      ((__bf16 *)dst)[e] = hi;
+    } else {
+      ((__bf16 *)dst)[2 * t * kTileElems + d] = hi;
+      ((__bf16 *)dst)[2 * t * kTileElems + kTileElems + d] = (__bf16)(h32 - (float)hi);
+    }
   }
 }
 }  // namespace
 
-hipError_t launch_split_bf16(const double *src, int64_t n_tiles, void *dst, hipStream_t s) {
+hipError_t launch_convert_tiles(const void *src, ttdft_dtype st, int64_t n_tiles, void *dst,
+                                ttdft_dtype dt, hipStream_t s) {
   const int64_t total = n_tiles * kTileElems;
   if (total == 0) return hipSuccess;
   const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 16384);
-  hipLaunchKernelGGL(split_bf16_kernel, dim3(g), dim3(256), 0, s, src, total, (__bf16 *)dst);
+  if (st == TTDFT_F64)
+    hipLaunchKernelGGL(convert_tiles_kernel<double>, dim3(g), dim3(256), 0, s, (const double *)src,
+                       total, dst, (int)dt);
+  else
+    hipLaunchKernelGGL(convert_tiles_kernel<float>, dim3(g), dim3(256), 0, s, (const float *)src,
+                       total, dst, (int)dt);
   return hipGetLastError();
+}
+
+hipError_t launch_split_bf16(const double *src, int64_t n_tiles, void *dst, hipStream_t s) {
+  return launch_convert_tiles(src, TTDFT_F64, n_tiles, dst, TTDFT_BF16_SPLIT, s);
 }
 
 namespace {

@@ -493,13 +493,15 @@ ttdft_status ttdft_density_matrix(const ttdft_bsr *H, const double *Psi, int64_t
   if (st != TTDFT_OK) return st;
   if (!Psi || !f || !P_vals) return failf(TTDFT_ERR_NULL, "Psi, f or P_vals is NULL");
   if (n_vec < 1 || ldp < n_vec) return failf(TTDFT_ERR_SHAPE, "bad shape");
+  if (!step_ld_ok(ldp, 8)) return failf(TTDFT_ERR_SHAPE, "leading dimension too large for 32-bit panel offsets");
   const int64_t rows = H->n_block_rows * 64;
   const size_t pb = block_bytes(rows, ldp, n_vec, 8), vb = (size_t)n_vec * 8;
   const size_t hb = (size_t)H->n_tiles * kTileElems * 8;
   if (overlap(P_vals, hb, Psi, pb) || overlap(P_vals, hb, f, vb) || overlap(P_vals, hb, H->vals, hb))
     return failf(TTDFT_ERR_ALIAS, "buffers overlap");
+  // P = 2 Psi diag(f) Psi^T is symmetric: each pair of mirror tiles is formed once
   hipError_t e = launch_sddmm(*H, Psi, ldp, Psi, ldp, n_vec, 2.0, P_vals, mask, false, TTDFT_F64,
-                              (hipStream_t)stream, f);
+                              (hipStream_t)stream, f, true);
   if (e != hipSuccess) return hip_fail(e, "density matrix launch");
   return api_ok();
 }

@@ -2,8 +2,9 @@
 // Chebyshev filter with respect to the stored entries of H:
 //     dH[t](i, j) (+)= coef * sum_c Abar[64*B + i][c] * Yk[64*B' + j][c]
 // for every stored tile t = (B, B'), entries outside the true pattern (mask bit
-// clear) written as 0.  dH has the layout of the tile values (fragment order:
-// entry (i, j) at 64*(4*(j/4) + i/16) + 16*(j%4) + i%16).  An optional weight
+// clear) written as 0.  dH has the layout of H's tile values (the fragment
+// order of H's type: tile_pos_16x4 for FP64 / FP32 tiles, tile_pos_16x32 for
+// BF16 tiles).  An optional weight
 // per vector c multiplies Abar[.][c] (the density matrix on the pattern of H is
 // this product with weights 2 f_c and Abar = Yk = Psi).  One work-group owns one tile and sweeps the vector
 // dimension in 16-wide panels, both operands staged transposed in LDS
@@ -12,7 +13,10 @@
 // current one is contracted (one barrier per panel).
 // FP64 inputs use the f64 16x16x4 op; FP32 and BF16 inputs accumulate in FP32
 // on the f32 16x16x4 op.  Each tile is written by one work-group in a fixed
-// order, so accumulation over the degree steps is deterministic.
+// order, so accumulation over the degree steps is deterministic.  A symmetric
+// product (Abar = Yk, the density matrix) computes only the tiles (B, B') with
+// B' >= B and writes each result also, transposed, into the mirror tile
+// (B', B): half the work.
 #include "ttdft_internal.h"
 
 namespace ttdft {
@@ -49,7 +53,7 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
     const int32_t *__restrict__ rowptr, const int32_t *__restrict__ tcol, int64_t n_block_rows,
     const TX *__restrict__ Abar, int64_t lda, const TX *__restrict__ Yk, int64_t ldb,
     int64_t n_vec, TC coef, TC *__restrict__ dH, const uint64_t *__restrict__ mask,
-    int accumulate, const double *__restrict__ colw) {
+    int accumulate, const double *__restrict__ colw, int frag32, int sym) {
   using O = Op<TC>;
   __shared__ TC sA[2][BK][64 + 1];
   __shared__ TC sB[2][BK][64 + 1];
@@ -61,6 +65,19 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
     if (rowptr[mid] <= t) lo = mid; else hi = mid;
   }
   const int64_t B = lo, Bc = tcol[t];
+  // symmetric product (Abar = Yk): tile (B', B) is the transpose of tile (B, B');
+  // the tile with B' > B computes both, the one with B' < B only when its
+  // mirror is not stored
+  int64_t tm = -1;
+  if (sym && Bc != B) {
+    int64_t a = rowptr[Bc], z = rowptr[Bc + 1];
+    while (a < z) {
+      const int64_t mid = (a + z) / 2;
+      if (tcol[mid] < B) a = mid + 1; else z = mid;
+    }
+    if (a < rowptr[Bc + 1] && tcol[a] == B) tm = a;
+    if (Bc < B && tm >= 0) return;
+  }
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const TX *Ar = Abar + B * 64 * lda;
   const TX *Br = Yk + Bc * 64 * ldb;
@@ -160,10 +177,19 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
     for (int q = 0; q < 4; ++q) {
       const int i = 16 * w + O::row(lane, q);
       const bool on = mask ? ((mask[t * 64 + i] >> j) & 1ull) != 0 : true;
-      const int pos = 64 * (4 * (j >> 2) + (i >> 4)) + 16 * (j & 3) + (i & 15);   // fragment order
+      const int pos = frag32 ? tile_pos_16x32(i, j) : tile_pos_16x4(i, j);   // layout of H's tiles
       TC v = coef * acc[jb][q];
       if (accumulate) v += out[pos];
       out[pos] = on ? v : TC(0);
+      if (tm >= 0) {
+        // entry (j, i) of the mirror tile: the same value
+        TC *out2 = dH + tm * kTileElems;
+        const bool on2 = mask ? ((mask[tm * 64 + j] >> i) & 1ull) != 0 : true;
+        const int pos2 = frag32 ? tile_pos_16x32(j, i) : tile_pos_16x4(j, i);
+        TC v2 = coef * acc[jb][q];
+        if (accumulate) v2 += out2[pos2];
+        out2[pos2] = on2 ? v2 : TC(0);
+      }
     }
   }
 }
@@ -172,22 +198,24 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
 
 hipError_t launch_sddmm(const ttdft_bsr &H, const void *Abar, int64_t lda, const void *Bk,
                         int64_t ldb, int64_t n_vec, double coef, void *dH, const uint64_t *mask,
-                        bool accumulate, ttdft_dtype xt, hipStream_t s, const double *colw) {
+                        bool accumulate, ttdft_dtype xt, hipStream_t s, const double *colw,
+                        bool sym) {
   if (H.n_tiles == 0) return hipSuccess;
   const dim3 grid((unsigned)H.n_tiles), block(THREADS);
   const int acc = accumulate ? 1 : 0;
+  const int f32o = (H.dtype == TTDFT_BF16 || H.dtype == TTDFT_BF16_SPLIT) ? 1 : 0;
   if (xt == TTDFT_F64)
     hipLaunchKernelGGL((sddmm_kernel<double, double>), grid, block, 0, s, H.tile_rowptr, H.tile_col,
                        H.n_block_rows, (const double *)Abar, lda, (const double *)Bk, ldb, n_vec,
-                       coef, (double *)dH, mask, acc, colw);
+                       coef, (double *)dH, mask, acc, colw, f32o, sym ? 1 : 0);
   else if (xt == TTDFT_F32)
     hipLaunchKernelGGL((sddmm_kernel<float, float>), grid, block, 0, s, H.tile_rowptr, H.tile_col,
                        H.n_block_rows, (const float *)Abar, lda, (const float *)Bk, ldb, n_vec,
-                       (float)coef, (float *)dH, mask, acc, colw);
+                       (float)coef, (float *)dH, mask, acc, colw, f32o, sym ? 1 : 0);
   else
     hipLaunchKernelGGL((sddmm_kernel<__bf16, float>), grid, block, 0, s, H.tile_rowptr, H.tile_col,
                        H.n_block_rows, (const __bf16 *)Abar, lda, (const __bf16 *)Bk, ldb, n_vec,
-                       (float)coef, (float *)dH, mask, acc, colw);
+                       (float)coef, (float *)dH, mask, acc, colw, f32o, sym ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -17,6 +17,23 @@ inline size_t tile_value_bytes(ttdft_dtype t) { return t == TTDFT_BF16_SPLIT ? 4
 constexpr int kTile = 64;                    // rows per lattice block (4x4x4)
 constexpr int64_t kTileElems = 64 * 64;
 
+// Positions of entry (i, j) inside a stored 64x64 tile.
+// FP64 / FP32 tiles: the 16x4 fragment order of the 16x16x4 matrix-core ops;
+// fragment (j/4, i/16) is 64 consecutive values, lane l taking value l
+// (row i%16 = l%16, column j%4 = l/16).
+__host__ __device__ inline int tile_pos_16x4(int i, int j) {
+  return 64 * (4 * (j >> 2) + (i >> 4)) + 16 * (j & 3) + (i & 15);
+}
+// BF16 tiles (and each half of a BF16_SPLIT tile): the 16x32 fragment order of
+// the 16x16x32 bf16 op; fragment (j/32, i/16) is 512 consecutive values and
+// lane l holds row i%16 = l%16, columns 8(l/16) .. 8(l/16)+7 of it as 16 bytes.
+__host__ __device__ inline int tile_pos_16x32(int i, int j) {
+  return 512 * (4 * (j >> 5) + (i >> 4)) + 8 * ((i & 15) + 16 * ((j & 31) >> 3)) + (j & 7);
+}
+__host__ __device__ inline int tile_pos(ttdft_dtype t, int i, int j) {
+  return (t == TTDFT_BF16 || t == TTDFT_BF16_SPLIT) ? tile_pos_16x32(i, j) : tile_pos_16x4(i, j);
+}
+
 // The step kernel addresses a 64-row panel of a dense block with 32-bit byte
 // offsets: 64 * ld * elt must fit in an int32.
 inline bool step_ld_ok(int64_t ld, size_t elt) { return ld >= 0 && 64 * ld * (int64_t)elt <= 0x7fffffffLL; }
@@ -35,6 +52,11 @@ ttdft_status filter_check(const ttdft_bsr *H, const void *X, int64_t ldx, const 
 ttdft_status filter_enqueue(const ttdft_bsr &H, const void *X, int64_t ldx, void *Y, int64_t ldy,
                             int64_t n_vec, int32_t m, double a, double b, double a0,
                             ttdft_dtype x_dtype, void *work, hipStream_t s);
+// as filter_enqueue, the steps k < m - m_late with H_early and the last m_late with H_late
+ttdft_status filter_enqueue_schedule(const ttdft_bsr &H_early, const ttdft_bsr &H_late, int32_t m_late,
+                                     const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t n_vec,
+                                     int32_t m, double a, double b, double a0, ttdft_dtype x_dtype,
+                                     void *work, hipStream_t s);
 // set the thread-local error string and return s
 ttdft_status api_fail(ttdft_status s, const char *msg);
 ttdft_status api_ok();
@@ -48,6 +70,9 @@ hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, con
 hipError_t launch_cast(const void *src, ttdft_dtype st, int64_t lds, void *dst, ttdft_dtype dt,
                        int64_t ldd, int64_t rows, int64_t cols, hipStream_t s);
 hipError_t launch_split_bf16(const double *src, int64_t n_tiles, void *dst, hipStream_t s);
+// tile values from F64 / F32 (16x4 order) to F32 (16x4), BF16 or BF16_SPLIT (16x32 order)
+hipError_t launch_convert_tiles(const void *src, ttdft_dtype st, int64_t n_tiles, void *dst,
+                                ttdft_dtype dt, hipStream_t s);
 // *count += number of NaN / Inf entries of a rows x cols block (count: device, cleared by the caller)
 hipError_t launch_count_nonfinite(const void *A, ttdft_dtype dt, int64_t ld, int64_t rows,
                                   int64_t cols, unsigned long long *count, hipStream_t s);
@@ -114,7 +139,7 @@ hipError_t run_syev(int64_t n, const double *A, int64_t lda, double *lambda, dou
 hipError_t launch_sddmm(const ttdft_bsr &H, const void *Abar, int64_t lda, const void *Bk,
                         int64_t ldb, int64_t n_vec, double coef, void *dH, const uint64_t *mask,
                         bool accumulate, ttdft_dtype xt, hipStream_t s,
-                        const double *colw = nullptr);
+                        const double *colw = nullptr, bool sym = false);
 
 // ---- occupancies and density (FP64)
 // mu with 2 sum_i f(lambda_i; mu) = n_electrons, f = Fermi-Dirac at kT; host_out = {mu, status}

@@ -82,6 +82,26 @@ def test_filter_validation(lib_built, kw, status):
     assert L.load().ttdft_last_error().decode() != ""
 
 
+def test_filter_schedule_validation(lib_built):
+    L = _lib()
+    lib = L.load()
+
+    def call(He=None, Hl=None, m_late=4, m=10, dt=1, work=FAKE * 100000, wb=1 << 40):
+        He = He if He is not None else _fake_bsr(dtype=2)
+        Hl = Hl if Hl is not None else _fake_bsr(dtype=1)
+        return L.STATUS[lib.ttdft_cheb_filter_schedule(C.byref(He), C.byref(Hl), m_late, FAKE, 16,
+                                                       FAKE * 1000, 16, 16, m, 2.0, 12.5, -3.0, dt,
+                                                       work, wb, None)]
+
+    assert call(m_late=11) == "TTDFT_ERR_DEGREE"
+    assert call(m_late=-1) == "TTDFT_ERR_DEGREE"
+    assert call(Hl=_fake_bsr(nbr=9, dtype=1)) == "TTDFT_ERR_SHAPE"
+    assert call(Hl=_fake_bsr(nt=65, dtype=1)) == "TTDFT_ERR_SHAPE"
+    assert call(Hl=_fake_bsr(dtype=0)) == "TTDFT_ERR_DTYPE"      # F64 tiles with F32 iterates
+    assert call(wb=10) == "TTDFT_ERR_WORKSPACE"
+    assert call(work=FAKE + 64) == "TTDFT_ERR_ALIAS"
+
+
 def test_filter_noalloc_validation(lib_built):
     # the same argument checks as ttdft_cheb_filter, and a work block larger than
     # the fixed 64 MiB scratch is rejected before any device work
@@ -143,7 +163,26 @@ def _bsr_host(r, h, dtype_code, seed=0):
     return (ip, ix, d, N), (nbr, nt, tptr, tcol, vals, perm, slot, mask, fmask)
 
 
-@pytest.mark.parametrize("r,h", [(4, 1), (6, 2), (10, 3), (8, 4), (5, 3)])
+def documented_block_coords(nb):
+    """Block number -> lattice block coordinates, from the numbering rule stated
+    with ttdft_bsr: complete 2x2x2 patches first, then incomplete ones."""
+    np_ = (nb + 1) // 2
+    out = []
+    for complete in (True, False):
+        for pi in range(np_):
+            for pj in range(np_):
+                for pk in range(np_):
+                    full = 2 * pi + 1 < nb and 2 * pj + 1 < nb and 2 * pk + 1 < nb
+                    if full != complete:
+                        continue
+                    for d in range(8):
+                        b = (2 * pi + (d >> 2), 2 * pj + ((d >> 1) & 1), 2 * pk + (d & 1))
+                        if max(b) < nb:
+                            out.append(b)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("r,h", [(4, 1), (6, 2), (10, 3), (8, 4), (5, 3), (12, 4)])
 def test_bsr_builder_roundtrip(lib_built, r, h):
     (ip, ix, d, N), (nbr, nt, tptr, tcol, vals, perm, slot, mask, fmask) = _bsr_host(r, h, 0)
     nb = (r + 3) // 4
@@ -176,13 +215,22 @@ def test_bsr_builder_roundtrip(lib_built, r, h):
     sub = bits.reshape(nt, 4, 16, 16, 4).any(axis=(2, 4))          # [t][mb][kk]
     fw = (sub.transpose(0, 2, 1).reshape(nt, 64).astype(np.uint64) * weights).sum(axis=1, dtype=np.uint64)
     np.testing.assert_array_equal(fw, fmask)
+    # block numbering as documented: complete 2x2x2 patches first (8 consecutive
+    # numbers each, blocks in (i, j, k) order, patches lexicographic), then the
+    # blocks of incomplete patches; the row of site (i, j, k) is 64*block + local
+    coords = documented_block_coords(nb)
+    assert sorted(map(tuple, coords)) == [(a, b, c) for a in range(nb) for b in range(nb) for c in range(nb)]
+    for row in np.flatnonzero(real)[:: max(1, real.sum() // 500)]:
+        I = perm[row]
+        i, j, k = I // (r * r), (I // r) % r, I % r
+        assert tuple(coords[row // 64]) == (i // 4, j // 4, k // 4)
+        assert row % 64 == 16 * (2 * ((i % 4) // 2) + (j % 4) // 2) + 4 * (2 * (i % 2) + j % 2) + k % 4
+    if nb >= 2:
+        assert [tuple(coords[q]) for q in range(8)] == [(a, b, c) for a in (0, 1) for b in (0, 1) for c in (0, 1)]
     # lattice blocking: every tile couples blocks at most one block apart per axis when h <= 4
     for B in range(nbr):
-        bi, bj, bk = B // (nb * nb), (B // nb) % nb, B % nb
         for t in range(tptr[B], tptr[B + 1]):
-            c = tcol[t]
-            ci, cj, ck = c // (nb * nb), (c // nb) % nb, c % nb
-            assert max(abs(ci - bi), abs(cj - bj), abs(ck - bk)) <= 1
+            assert np.abs(coords[tcol[t]] - coords[B]).max() <= 1
 
 
 def test_bsr_builder_low_precision_rounding(lib_built):
@@ -192,6 +240,32 @@ def test_bsr_builder_low_precision_rounding(lib_built):
     (ip, ix, d, N), (_, _, _, _, v16, _, slot, _, _) = _bsr_host(5, 2, 2)
     ref = torch.from_numpy(d.astype(np.float32)).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
     np.testing.assert_array_equal(v16[slot], ref)
+
+
+def test_bsr_builder_bf16_fragment_order(lib_built):
+    # BF16 tiles are stored in the 16x32 fragment order of the bf16 op: entry
+    # (i, j) of tile t at t*4096 + 512*(4*(j//32) + i//16) + 8*(i%16 + 16*((j%32)//8)) + j%8,
+    # the same entries as the FP64 tiles (16x4 order) hold
+    from paper_2110_15853_amd.api import _slots_16x32
+    (_, _, d, _), (_, nt, _, _, v64, _, s64, _, _) = _bsr_host(6, 3, 0)
+    (_, _, _, _), (_, nt16, _, _, v16, _, s16, _, _) = _bsr_host(6, 3, 2)
+    assert nt16 == nt
+    ii, jj = np.meshgrid(np.arange(64), np.arange(64), indexing="ij")
+    p4 = 64 * (4 * (jj // 4) + ii // 16) + 16 * (jj % 4) + ii % 16
+    p32 = 512 * (4 * (jj // 32) + ii // 16) + 8 * (ii % 16 + 16 * ((jj % 32) // 8)) + jj % 8
+    assert sorted(p32.ravel()) == list(range(4096))
+    t, p = np.divmod(s64, 4096)
+    inv4 = np.empty(4096, np.int64)
+    inv4[p4.ravel()] = np.arange(4096)
+    want = t * 4096 + p32.ravel()[inv4[p]]
+    np.testing.assert_array_equal(s16, want)
+    np.testing.assert_array_equal(_slots_16x32(s64, 4096), want)
+    import torch
+    ref = torch.from_numpy(d.astype(np.float32)).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    np.testing.assert_array_equal(v16[want], ref)
+    stored = np.zeros(nt * 4096, bool)
+    stored[want] = True
+    assert not v16[~stored].any()
 
 
 def test_bsr_builder_rejects_bad_csr(lib_built):
@@ -333,7 +407,8 @@ def test_bsr_builder_bf16_split(lib_built):
     assert lib.ttdft_bsr_build(5, P(ip), P(ix), P(d), 3, P(tptr3), P(tcol3), P(vs), P(perm3), P(slot3),
                                None, None) == 0
     assert np.array_equal(tptr3, tptr) and np.array_equal(tcol3, tcol) and np.array_equal(perm3, perm)
-    np.testing.assert_array_equal(slot3, (slot // 4096) * 8192 + slot % 4096)
+    from paper_2110_15853_amd.api import _slots_16x32     # hi values in the BF16 fragment order
+    np.testing.assert_array_equal(slot3, _slots_16x32(slot, 8192))
     bf = lambda u: torch.from_numpy(u.view(np.int16)).view(torch.bfloat16).float().numpy().astype(np.float64)
     hi, lo = bf(vs[slot3]), bf(vs[slot3 + 4096])
     h32 = d.astype(np.float32)
