@@ -322,14 +322,14 @@ __global__ __launch_bounds__(PB_THREADS, 1) void cheb_step_bf16_patch(
   constexpr int TILE_VALS = 4096 * PARTS;                  // bf16 values per stored tile
   constexpr int XFER = TILE_VALS * 2 / (PB_THREADS * 16);  // 16-byte H transfers per lane per tile
   constexpr int YX = 32 / PB_WAVES;                        // two-row Y transfers per wave per panel
-  constexpr int HS = SPLIT ? 4 : 8;                        // H ring stages
+  constexpr int HS = SPLIT ? 5 : 10;                       // H ring slots (tiles)
   static_assert(!SPLIT || sizeof(TX) == 4, "split products need FP32 iterates");
   __shared__ __attribute__((aligned(16))) __bf16 sH[HS][TILE_VALS];
   __shared__ __attribute__((aligned(16))) char sY[YDMA ? PB_YS * 32 * PB_YCH : 16];
-  __shared__ int s_val[PB_CAP], s_row[PB_CAP], s_first[PB_CAP], s_ucol[PB_CAP], s_seq[PB_CAP];
-  __shared__ int s_ut[PB_CAP][PB_R];
+  __shared__ int s_val[PB_CAP], s_row[PB_CAP], s_first[PB_CAP], s_seq[PB_CAP];
+  __shared__ int s_ucol[PB_CAP + 1], s_ustart[PB_CAP + 1], s_umask[PB_CAP + 1];
   __shared__ int s_rp[PB_R + 1];
-  __shared__ int s_recH[PB_WAVES][HS], s_recY[PB_WAVES][PB_YS];
+  __shared__ int s_hcnt[PB_WAVES][HS];
 
   const int64_t n_patch = (n_block_rows + PB_R - 1) / PB_R;
   const int64_t L = group_order(blockIdx.x, n_wg, cgroup);
@@ -356,10 +356,8 @@ __global__ __launch_bounds__(PB_THREADS, 1) void cheb_step_bf16_patch(
     for (int mb = 0; mb < 4; ++mb) acc[i][mb] = v4f{0, 0, 0, 0};
 
   const int32_t panel_bytes = (int32_t)(64 * ldk * (int64_t)sizeof(TX));
-  // memory instructions this wave has issued for the two rings (wave-uniform)
-  int nH = 0, nY = 0;
 
-  // ---- H tile t into ring stage st (16 bytes per lane, fragment order kept)
+  // ---- H tile t into ring slot st (16 bytes per lane, fragment order kept)
   auto dma_h = [&](int t, int st) {
     const __bf16 *src = vals + (int64_t)t * TILE_VALS + (w * XFER) * 512 + 8 * lane;
 #pragma unroll
@@ -424,8 +422,8 @@ __global__ __launch_bounds__(PB_THREADS, 1) void cheb_step_bf16_patch(
         if (SPLIT) bl[kk][t] = (__bf16)(v - (float)bh[kk][t]);
       }
   };
-  // all A fragments of the tile are read from LDS before the matrix-core ops,
-  // so the LDS latency is paid once per tile, not once per op
+  // all A fragments of a tile are read from LDS before its matrix-core ops, so
+  // the LDS latency is paid once per tile
   auto mma_tile = [&](v4f (&ac)[4], const __bf16 *sA) {
     v8bf a[8], alo[SPLIT ? 8 : 1];
 #pragma unroll
@@ -446,22 +444,6 @@ __global__ __launch_bounds__(PB_THREADS, 1) void cheb_step_bf16_patch(
         }
       }
   };
-  // issue helpers that record, per ring slot, the other ring's count at issue
-  auto issue_h = [&](int p) {
-    dma_h(__builtin_amdgcn_readfirstlane(s_seq[p]), p % HS);
-    s_recH[w][p % HS] = nY;
-    ++nH;
-  };
-  auto issue_y = [&](int u) {
-    const int64_t Bc = __builtin_amdgcn_readfirstlane(s_ucol[u]);
-    if constexpr (YDMA) {
-      dma_y(Bc, u % PB_YS);
-      s_recY[w][u % PB_YS] = nH;
-      ++nY;
-    } else {
-      load_y_regs(Bc);
-    }
-  };
 
   __syncthreads();
   const int e_all0 = s_rp[0], e_all1 = s_rp[nrows];
@@ -473,16 +455,16 @@ __global__ __launch_bounds__(PB_THREADS, 1) void cheb_step_bf16_patch(
     for (int e_begin = r0; e_begin < r1; e_begin += PB_CAP) {
       const int ne = min(PB_CAP, r1 - e_begin);
       // ---- union schedule of this segment (LDS): distinct block columns in
-      // ascending order (union steps u), per step the tile of each patch row,
-      // and the tile sequence in (u, row) order
+      // ascending order (union steps u) with the patch rows holding a tile there
+      // (bit mask) and the first sequence position of the step; the tile
+      // sequence in (column, row) order
       for (int e = tid; e < ne; e += PB_THREADS) {
         const int tt = e_begin + e;
         s_val[e] = tcol[tt];
         int i = 0;
         while (i + 1 < nrows && s_rp[i + 1] <= tt) ++i;
         s_row[e] = i;
-#pragma unroll
-        for (int r = 0; r < PB_R; ++r) s_ut[e][r] = -1;
+        s_umask[e] = 0;
       }
       __syncthreads();
       for (int e = tid; e < ne; e += PB_THREADS) {
@@ -494,54 +476,90 @@ __global__ __launch_bounds__(PB_THREADS, 1) void cheb_step_bf16_patch(
       __syncthreads();
       for (int e = tid; e < ne; e += PB_THREADS) {
         const int v = s_val[e], i = s_row[e];
-        int u = 0, pos = 0;
+        int u = 0, pos = 0, before = 0;
         for (int e2 = 0; e2 < ne; ++e2) {
           const int v2 = s_val[e2];
           u += (s_first[e2] && v2 < v);
+          before += (v2 < v);
           pos += (v2 < v || (v2 == v && s_row[e2] < i));
         }
-        s_ut[u][i] = e_begin + e;
-        if (s_first[e]) s_ucol[u] = v;
+        atomicOr(&s_umask[u], 1 << i);
+        if (s_first[e]) {
+          s_ucol[u] = v;
+          s_ustart[u] = before;
+        }
         s_seq[pos] = e_begin + e;
       }
       __syncthreads();
       int nu = 0;
       for (int e = 0; e < ne; ++e) nu += s_first[e];
+      if (tid == 0) s_ustart[nu] = ne;
+      __syncthreads();
 
-      // ---- pipeline: H tiles HS - 1 ahead in sequence order, the Y_k panel
-      // two union steps ahead
-      nH = 0;
-      nY = 0;
-      for (int p = 0; p < HS - 1 && p < ne; ++p) issue_h(p);
-      if (nu > 0) issue_y(0);
-      if (YDMA && nu > 1) issue_y(1);
-      int pos = 0;
-      for (int u = 0; u < nu; ++u) {
-        if constexpr (YDMA) {
-          // this wave's transfers of panel u are done when at most the memory
-          // instructions issued after them are outstanding
-          wait_vmcnt_le(YX * (nY - 1 - u) + XFER * (nH - s_recY[w][u % PB_YS]));
-          __syncthreads();               // every wave's part of panel u is in LDS
-          convert_y(u % PB_YS);
-          __syncthreads();               // every wave has its copy: the stage takes panel u + 2
-          if (u + 2 < nu) issue_y(u + 2);
-        } else {
-          convert_y(0);
-          if (u + 1 < nu) issue_y(u + 1);
+      // ---- pipeline at union-step granularity: one wait and one barrier per
+      // step.  H tiles go to ring slot (position % HS) as far ahead as the ring
+      // allows, the Y_k panel one step ahead.  Each wave counts the memory
+      // instructions it has issued and records the count after each transfer
+      // (H: per ring slot, in LDS), so it waits for exactly those a step needs.
+      int issued = 0, next_h = 0, need_y[2] = {0, 0};
+      auto issue_h_upto = [&](int lim) {     // positions next_h .. lim-1
+        for (; next_h < lim; ++next_h) {
+          dma_h(__builtin_amdgcn_readfirstlane(s_seq[next_h]), next_h % HS);
+          issued += XFER;
+          s_hcnt[w][next_h % HS] = issued;
         }
+      };
+      auto issue_y = [&](int u) {
+        if constexpr (YDMA) {
+          dma_y(__builtin_amdgcn_readfirstlane(s_ucol[u]), u & 1);
+          issued += YX;
+          need_y[u & 1] = issued;
+        } else {
+          load_y_regs(__builtin_amdgcn_readfirstlane(s_ucol[u]));
+        }
+      };
+      issue_h_upto(min(HS, ne));
+      if (nu > 0) issue_y(0);
+      for (int u = 0; u < nu; ++u) {
+        const int s0 = s_ustart[u], s1 = s_ustart[u + 1];
+        const int um = __builtin_amdgcn_readfirstlane(s_umask[u]);
+        // the step's tiles in chunks of at most HS positions (one chunk unless the
+        // step holds more tiles than the ring)
+        for (int p = s0; p < s1; p += HS) {
+          const int pe = min(s1, p + HS);
+          if (next_h < pe) {
+            // positions up to pe - 1 take the slots of positions before p, read by
+            // the products of the previous chunk or step: wait for every wave
+            __syncthreads();
+            issue_h_upto(min(p + HS, ne));
+          }
+          int need = s_hcnt[w][(pe - 1) % HS];
+          if constexpr (YDMA) {
+            if (p == s0) need = max(need, need_y[u & 1]);
+          }
+          wait_vmcnt_le(issued - need);
+          __syncthreads();   // the chunk's transfers (every wave's part) are in LDS;
+                             // the slots of earlier positions and step u-1's Y stage are free
+          if (p == s0) {
+            if constexpr (YDMA) {
+              if (u + 1 < nu) issue_y(u + 1);
+              convert_y(u & 1);
+            } else {
+              convert_y(0);
+              if (u + 1 < nu) issue_y(u + 1);
+            }
+          }
+          issue_h_upto(min(p + HS, ne));   // slots of positions < p are free
+          int pos = s0;
 #pragma unroll
-        for (int i = 0; i < PB_R; ++i) {
-          const int t = __builtin_amdgcn_readfirstlane(s_ut[u][i]);
-          if (t < 0) continue;
-          // tile `pos`: done when at most the instructions issued after it are outstanding
-          wait_vmcnt_le(XFER * (nH - 1 - pos) + YX * (nY - s_recH[w][pos % HS]));
-          __syncthreads();               // every wave's part is in LDS; stage pos-1 is free
-          if (pos + HS - 1 < ne) issue_h(pos + HS - 1);
-          mma_tile(acc[i], sH[pos % HS]);
-          ++pos;
+          for (int i = 0; i < PB_R; ++i) {
+            if (!((um >> i) & 1)) continue;
+            if (pos >= p && pos < pe) mma_tile(acc[i], sH[pos % HS]);
+            ++pos;
+          }
         }
       }
-      __syncthreads();   // the schedule arrays are rebuilt by the next segment
+      __syncthreads();   // the schedule arrays and slots are reused by the next segment
     }
   }
 
