@@ -32,11 +32,15 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM-side bytes per launch of the dominant kernel from the two rocprofv3 counter
 # passes (FETCH_SIZE, WRITE_SIZE), calibrated against a plain copy of known size;
-# see profiles/cheb_step_f64_lattice60_h4_n2048_m20_bytes.md.  Valid only while the
-# kernel source is the one that was profiled.
+# see profiles/cheb_step_<precision>_lattice60_h4_n2048_m20_bytes.md.  Valid only while
+# the kernel source is the one that was profiled.
 COUNTED_TRAFFIC = {
-    ("f64", "lattice60_h4_n2048_m20"): {"read_bytes": 93.856e9, "write_bytes": 3.539e9,
-                                        "kernel_sha256_16": "c36edb4d35ed3ad1"},
+    ("f64", "lattice60_h4_n2048_m20"): {"read_bytes": 90.855e9, "write_bytes": 3.539e9,
+                                        "kernel_sha256_16": "29cdfc5b37a4e460"},
+    ("bf16", "lattice60_h4_n2048_m20"): {"read_bytes": 16.221e9, "write_bytes": 1.774e9,
+                                        "kernel_sha256_16": "29cdfc5b37a4e460"},
+    ("bf16x3", "lattice60_h4_n2048_m20"): {"read_bytes": 16.960e9, "write_bytes": 1.772e9,
+                                        "kernel_sha256_16": "29cdfc5b37a4e460"},
 }
 
 
@@ -168,7 +172,10 @@ def mixed_precision_report(P, torch, ip, ix, d, cfg, H64, Xb64, keep_frac=1800 /
                "alg_gflops": round(2.0 * nnz * cfg.n * cfg.m / (tl / 1e3) / 1e9, 1)}
         if ml == 0:
             hb = tiles[early].vals.numel() * tiles[early].vals.element_size()
-            rec["roofline"] = step_roofline(early, 2.0 * nnz * cfg.n, hb + x_bytes, tl / 1e3 / cfg.m)
+            counted = COUNTED_TRAFFIC.get((early, cfg.name))
+            traffic = (counted["read_bytes"] + counted["write_bytes"]
+                       if counted and counted["kernel_sha256_16"] == kernel_source_sha16() else None)
+            rec["roofline"] = step_roofline(early, 2.0 * nnz * cfg.n, hb + x_bytes, tl / 1e3 / cfg.m, traffic)
             rec["roofline"]["alg_bytes_per_launch"] = hb + x_bytes
         for regime, X0, lam_ref, psi_ref in (("cold", Xl, lam_c, psi_c),
                                              ("warm", P.cast(Xw, torch.float32), lam_w, psi_w)):
