@@ -270,17 +270,20 @@ template <> __device__ inline __bf16 buffer_load<__bf16>(__amdgpu_buffer_rsrc_t 
 // The BF16 step is bound by bytes, and the panels (not the 4x smaller tiles)
 // are most of them: this cuts the panel reads by 27*8/64.
 //  - A (H tiles, 16x32 fragment order) moved to LDS by LDS-DMA through a ring
-//    of HS stages, one tile per step, HS - 1 tiles ahead;
+//    of HS tile slots, as far ahead as the ring allows;
 //  - B (Y_k panel): FP32 iterates moved to LDS by buffer LDS-DMA (range-checked
-//    against the panel) through a ring of 2 stages, two union steps ahead (a
-//    stage is free again once every lane has read its 8 rows of its vector and
-//    rounded them to bf16 at the start of its step; SPLIT: hi = bf16(y),
-//    lo = bf16(y - hi)); rows padded so the reads hit 64 distinct banks; BF16
-//    iterates are read into registers by buffer loads one union step ahead;
+//    against the panel) through a ring of PB_YS stages, PB_YS - 1 union steps
+//    ahead (a stage is free again once every lane has read its 8 rows of its
+//    vector and rounded them to bf16 at the start of its step; SPLIT:
+//    hi = bf16(y), lo = bf16(y - hi)); rows padded so the reads hit 64
+//    distinct banks; BF16 iterates are read into registers by buffer loads one
+//    union step ahead;
 //  - completion of each wave's transfers is tracked by counting the memory
-//    instructions it issued after the one waited for (rings of issue counts
-//    in LDS) and waited for with s_waitcnt (a jump over the possible counts)
-//    before a barrier;
+//    instructions it issued after the one waited for (the count after each
+//    ring slot's and stage's transfer kept in a lane of a register) and waited
+//    for with s_waitcnt (a jump over the possible counts) before a barrier;
+//  - the tile ids of a refill are read from LDS with one vector read and taken
+//    lane by lane, and ring slots are followed by counters (no division);
 //  - every 16x32 fragment of a tile is contracted: skipping the empty ones
 //    (16% at h = 4) saves matrix-core work, which is not what bounds this step,
 //    and costs a scalar test per fragment;
@@ -288,6 +291,11 @@ template <> __device__ inline __bf16 buffer_load<__bf16>(__amdgpu_buffer_rsrc_t 
 // Patches with more than PB_CAP tiles (not produced by stencils with h <= 4) are
 // walked one block row at a time in chunks of PB_CAP tiles.
 constexpr int PB_R = 8, PB_WAVES = 8, PB_THREADS = 64 * PB_WAVES, PB_NV = 16 * PB_WAVES;
+// launch order of the patch kernel: column groups of PB_CGROUP column tiles
+// outermost; each XCD takes runs of PB_RUN consecutive patches (all column tiles
+// of the group), so that neighbouring patches, which share half of their
+// neighbour panels, run on one XCD at the same time
+constexpr int PB_CGROUP = 16, PB_RUN = 1;
 constexpr int PB_CAP = 27 * PB_R;
 constexpr int PB_YS = 2;                 // Y panel ring stages
 constexpr int PB_YCH = 1024 + 16;        // bytes per two-row chunk of an FP32 panel in LDS
@@ -322,17 +330,18 @@ __global__ __launch_bounds__(PB_THREADS, 1) void cheb_step_bf16_patch(
   constexpr int TILE_VALS = 4096 * PARTS;                  // bf16 values per stored tile
   constexpr int XFER = TILE_VALS * 2 / (PB_THREADS * 16);  // 16-byte H transfers per lane per tile
   constexpr int YX = 32 / PB_WAVES;                        // two-row Y transfers per wave per panel
-  constexpr int HS = SPLIT ? 5 : 10;                       // H ring slots (tiles)
+  // H ring slots (tiles): what the LDS leaves beside the Y ring
+  constexpr int HS = !YDMA ? 10 : SPLIT ? (PB_YS == 2 ? 5 : 3) : (PB_YS == 2 ? 10 : 6);
+  static_assert(HS <= 64 && PB_YS <= 64, "issue counts are kept one per lane");
   static_assert(!SPLIT || sizeof(TX) == 4, "split products need FP32 iterates");
   __shared__ __attribute__((aligned(16))) __bf16 sH[HS][TILE_VALS];
   __shared__ __attribute__((aligned(16))) char sY[YDMA ? PB_YS * 32 * PB_YCH : 16];
   __shared__ int s_val[PB_CAP], s_row[PB_CAP], s_first[PB_CAP], s_seq[PB_CAP];
   __shared__ int s_ucol[PB_CAP + 1], s_ustart[PB_CAP + 1], s_umask[PB_CAP + 1];
   __shared__ int s_rp[PB_R + 1];
-  __shared__ int s_hcnt[PB_WAVES][HS];
 
   const int64_t n_patch = (n_block_rows + PB_R - 1) / PB_R;
-  const int64_t L = group_order(blockIdx.x, n_wg, cgroup);
+  const int64_t L = group_order(blockIdx.x, n_wg, cgroup * PB_RUN);
   const int64_t per_group = n_patch * cgroup;
   const int64_t cg = L / per_group, rem = L % per_group;
   const int64_t B0 = (rem / cgroup) * PB_R;
@@ -498,28 +507,42 @@ __global__ __launch_bounds__(PB_THREADS, 1) void cheb_step_bf16_patch(
 
       // ---- pipeline at union-step granularity: one wait and one barrier per
       // step.  H tiles go to ring slot (position % HS) as far ahead as the ring
-      // allows, the Y_k panel one step ahead.  Each wave counts the memory
-      // instructions it has issued and records the count after each transfer
-      // (H: per ring slot, in LDS), so it waits for exactly those a step needs.
-      int issued = 0, next_h = 0, need_y[2] = {0, 0};
-      auto issue_h_upto = [&](int lim) {     // positions next_h .. lim-1
-        for (; next_h < lim; ++next_h) {
-          dma_h(__builtin_amdgcn_readfirstlane(s_seq[next_h]), next_h % HS);
+      // allows, the Y_k panel of step u to stage u % PB_YS, PB_YS - 1 steps
+      // ahead.  Each wave counts the memory instructions it has issued and keeps
+      // the count after each slot's (hc) and stage's (yc) transfer in the lane
+      // of that slot or stage, so it waits for exactly those a step needs.
+      int issued = 0, next_h = 0, h_slot = 0;   // h_slot = next_h % HS
+      int hc = 0, yc = 0;
+      auto issue_h_upto = [&](int lim) {     // positions next_h .. lim-1 (at most HS)
+        const int cnt = lim - next_h;
+        if (cnt <= 0) return;
+        const int sq = s_seq[min(next_h + lane, lim - 1)];
+        for (int j = 0; j < cnt; ++j) {
+          dma_h(__builtin_amdgcn_readlane(sq, j), h_slot);
           issued += XFER;
-          s_hcnt[w][next_h % HS] = issued;
+          hc = lane == h_slot ? issued : hc;
+          h_slot = h_slot + 1 == HS ? 0 : h_slot + 1;
         }
+        next_h = lim;
       };
-      auto issue_y = [&](int u) {
+      // ring slot of position q, for next_h - HS <= q < next_h
+      auto slot_of = [&](int q) {
+        const int sl = h_slot - (next_h - q);
+        return sl < 0 ? sl + HS : sl;
+      };
+      auto issue_y = [&](int u, int st) {
         if constexpr (YDMA) {
-          dma_y(__builtin_amdgcn_readfirstlane(s_ucol[u]), u & 1);
+          dma_y(__builtin_amdgcn_readfirstlane(s_ucol[u]), st);
           issued += YX;
-          need_y[u & 1] = issued;
+          yc = lane == st ? issued : yc;
         } else {
           load_y_regs(__builtin_amdgcn_readfirstlane(s_ucol[u]));
         }
       };
       issue_h_upto(min(HS, ne));
-      if (nu > 0) issue_y(0);
+      constexpr int YAHEAD = YDMA ? PB_YS - 1 : 1;
+      for (int u = 0; u < min(YAHEAD, nu); ++u) issue_y(u, u);
+      int y_cur = 0;                          // stage of step u
       for (int u = 0; u < nu; ++u) {
         const int s0 = s_ustart[u], s1 = s_ustart[u + 1];
         const int um = __builtin_amdgcn_readfirstlane(s_umask[u]);
@@ -533,31 +556,36 @@ __global__ __launch_bounds__(PB_THREADS, 1) void cheb_step_bf16_patch(
             __syncthreads();
             issue_h_upto(min(p + HS, ne));
           }
-          int need = s_hcnt[w][(pe - 1) % HS];
+          int need = __builtin_amdgcn_readlane(hc, slot_of(pe - 1));
           if constexpr (YDMA) {
-            if (p == s0) need = max(need, need_y[u & 1]);
+            if (p == s0) need = max(need, __builtin_amdgcn_readlane(yc, y_cur));
           }
           wait_vmcnt_le(issued - need);
           __syncthreads();   // the chunk's transfers (every wave's part) are in LDS;
                              // the slots of earlier positions and step u-1's Y stage are free
           if (p == s0) {
             if constexpr (YDMA) {
-              if (u + 1 < nu) issue_y(u + 1);
-              convert_y(u & 1);
+              if (u + YAHEAD < nu) issue_y(u + YAHEAD, y_cur == 0 ? PB_YS - 1 : y_cur - 1);
+              convert_y(y_cur);
             } else {
               convert_y(0);
-              if (u + 1 < nu) issue_y(u + 1);
+              if (u + 1 < nu) issue_y(u + 1, 0);
             }
           }
           issue_h_upto(min(p + HS, ne));   // slots of positions < p are free
+          const int slot_p = slot_of(p);
           int pos = s0;
 #pragma unroll
           for (int i = 0; i < PB_R; ++i) {
             if (!((um >> i) & 1)) continue;
-            if (pos >= p && pos < pe) mma_tile(acc[i], sH[pos % HS]);
+            if (pos >= p && pos < pe) {
+              const int sl = slot_p + (pos - p);
+              mma_tile(acc[i], sH[sl >= HS ? sl - HS : sl]);
+            }
             ++pos;
           }
         }
+        if constexpr (YDMA) y_cur = y_cur + 1 == PB_YS ? 0 : y_cur + 1;
       }
       __syncthreads();   // the schedule arrays and slots are reused by the next segment
     }
@@ -621,7 +649,7 @@ hipError_t launch_cheb_step(const ttdft_bsr &H, const void *Yk, int64_t ldk, con
                          H.frag_mask);
   } else {
     const int64_t ctp = (n_vec + PB_NV - 1) / PB_NV;
-    const int64_t cgroup = std::min<int64_t>(ctp, ORDER_CGROUP);
+    const int64_t cgroup = std::min<int64_t>(ctp, PB_CGROUP);
     const int64_t n_groups = (ctp + cgroup - 1) / cgroup;
     const int64_t n_patch = (H.n_block_rows + PB_R - 1) / PB_R;
     const int64_t wg = n_groups * n_patch * cgroup;
