@@ -155,6 +155,114 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_tn_kernel(
     }
 }
 
+// ---------------------------------------------------------------- C = A^T B, split K, LDS-DMA
+// The same tiles and waves as gemm_tn_kernel, with the panels moved straight into
+// LDS (global_load_lds_dwordx4, no register staging) through a ring of DMA_STAGES
+// panels of DMA_PK k-rows, issued DMA_STAGES - 1 panels ahead (after the first
+// quarter of the current panel's products, so that the issue overlaps them), one
+// work-group per CU.  For whole panels only: n a multiple of 128, K a multiple
+// of DMA_PK, operands 16-byte aligned (checked on the host; other shapes take
+// gemm_tn_kernel).
+constexpr int DMA_PK = 16, DMA_STAGES = 4;
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+template <int N> __device__ inline void gemm_wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+__global__ __launch_bounds__(THREADS, 1) void gemm_tn_dma_kernel(
+    const double *__restrict__ A, int64_t lda, const double *__restrict__ B, int64_t ldb,
+    int64_t K, int64_t n, double *__restrict__ partial, int64_t k_per_split, int tiles_n,
+    int sym) {
+  constexpr int RW = DMA_PK / 4;          // k-rows of each operand a wave moves per panel
+  constexpr int XF = 2 * RW;              // transfers per wave per panel
+  __shared__ __attribute__((aligned(16))) double sA[DMA_STAGES][DMA_PK][LDS_LD];
+  __shared__ __attribute__((aligned(16))) double sB[DMA_STAGES][DMA_PK][LDS_LD];
+  int ti, tj;
+  if (sym) {  // linear index over lower-triangular tile pairs (ti >= tj)
+    int t = blockIdx.x;
+    ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    while (ti * (ti + 1) / 2 > t) --ti;
+    tj = t - ti * (ti + 1) / 2;
+  } else {
+    ti = blockIdx.x / tiles_n;
+    tj = blockIdx.x % tiles_n;
+  }
+  const int64_t i0 = (int64_t)ti * BM, j0 = (int64_t)tj * BN;
+  const int64_t kb = (int64_t)blockIdx.y * k_per_split;
+  const int64_t ke = min(K, kb + k_per_split);
+  const int np = kb < ke ? (int)((ke - kb) / DMA_PK) : 0;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
+
+  // wave w moves k-rows w, w + 4, ... of both operands of a panel: one 1 KB row
+  // (128 doubles) per transfer, 16 bytes per lane; the lane's addresses are its
+  // row-w address plus a wave-uniform offset
+  const double *a_lane = A + (kb + w) * lda + i0 + 2 * lane;
+  const double *b_lane = B + (kb + w) * ldb + j0 + 2 * lane;
+  auto issue = [&](int p) {
+    const int st = p % DMA_STAGES;
+    const int64_t ka = (int64_t)p * DMA_PK * lda, kbb = (int64_t)p * DMA_PK * ldb;
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      const int r = w + 4 * q;
+      const uint32_t la = (uint32_t)(uintptr_t)(lds_void_t *)(&sA[st][r][0]);
+      const uint32_t lb = (uint32_t)(uintptr_t)(lds_void_t *)(&sB[st][r][0]);
+      asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                   :
+                   : "s"(__builtin_amdgcn_readfirstlane(la)), "v"(a_lane + ka + 4 * q * lda)
+                   : "memory", "m0");
+      asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                   :
+                   : "s"(__builtin_amdgcn_readfirstlane(lb)), "v"(b_lane + kbb + 4 * q * ldb)
+                   : "memory", "m0");
+    }
+  };
+
+  v4d acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+  for (int p = 0; p < min(DMA_STAGES - 1, np); ++p) issue(p);
+  for (int p = 0; p < np; ++p) {
+    // this wave's transfers of panel p are done once at most those of the panels
+    // issued after it (p + 1 .. p + DMA_STAGES - 2) are outstanding
+    const int after = min(DMA_STAGES - 2, np - 1 - p);
+    if (after >= 2) gemm_wait_vmcnt<2 * XF>();
+    else if (after == 1) gemm_wait_vmcnt<XF>();
+    else gemm_wait_vmcnt<0>();
+    __syncthreads();   // every wave's part of panel p is in LDS; panel p - 1's stage is free
+    const int st = p % DMA_STAGES;
+#pragma unroll
+    for (int kq = 0; kq < DMA_PK; kq += 4) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = sA[st][kq + (lane >> 4)][64 * wm + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = sB[st][kq + (lane >> 4)][64 * wn + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
+      if (kq == 0 && p + DMA_STAGES - 1 < np) issue(p + DMA_STAGES - 1);
+    }
+  }
+  double *P = partial + (int64_t)blockIdx.y * n * n;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t col = j0 + 64 * wn + 16 * j + (lane & 15);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t row = i0 + 64 * wm + 16 * i + out_row(lane, t);
+        P[row * n + col] = acc[i][j][t];
+      }
+    }
+}
+
 // C[i][j] = sum_s partial[s][i][j] in order s = 0, 1, ...; sym mirrors the
 // lower-triangular tiles; symmetrize writes (P + P^T)/2 (with sym: inside the
 // diagonal tiles, the only ones holding both P_ij and P_ji).
@@ -329,8 +437,15 @@ hipError_t launch_gemm_tn_ex(const double *A, int64_t lda, const double *B, int6
   const int64_t n_tiles = sym ? (int64_t)tiles_n * (tiles_n + 1) / 2 : (int64_t)tiles_n * tiles_n;
   int64_t kps = (rows + splits - 1) / splits;
   kps = (kps + BK - 1) / BK * BK;
-  hipLaunchKernelGGL(gemm_tn_kernel, dim3((unsigned)n_tiles, (unsigned)splits), dim3(THREADS), 0,
-                     s, A, lda, B, ldb, rows, n, partial, kps, tiles_n, sym ? 1 : 0);
+  const bool whole = n % BM == 0 && rows % DMA_PK == 0 && kps % DMA_PK == 0 && lda % 2 == 0 &&
+                     ldb % 2 == 0 &&
+                     ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0;
+  if (whole)
+    hipLaunchKernelGGL(gemm_tn_dma_kernel, dim3((unsigned)n_tiles, (unsigned)splits), dim3(THREADS),
+                       0, s, A, lda, B, ldb, rows, n, partial, kps, tiles_n, sym ? 1 : 0);
+  else
+    hipLaunchKernelGGL(gemm_tn_kernel, dim3((unsigned)n_tiles, (unsigned)splits), dim3(THREADS), 0,
+                       s, A, lda, B, ldb, rows, n, partial, kps, tiles_n, sym ? 1 : 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t total = n * n;

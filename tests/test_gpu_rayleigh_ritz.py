@@ -15,8 +15,11 @@ def _cuda(x):
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
 
 
+# (4096, 256) and (1600, 128): whole 128-column tiles and 16-row panels, which the Gram
+# product moves by LDS-DMA; the other shapes take the register-staged tile
 @pytest.mark.parametrize("rows,n,cond_exp", [(3000, 100, 4), (1000, 37, 2), (700, 130, 6),
-                                             (64, 64, 1), (5000, 1, 0), (2049, 257, 3)])
+                                             (64, 64, 1), (5000, 1, 0), (2049, 257, 3),
+                                             (4096, 256, 3), (1600, 128, 1)])
 def test_cholqr2_matches_householder(rows, n, cond_exp):
     print(f"cholqr2 rows={rows} n={n}", flush=True)
     torch, P = require_gpu()
@@ -169,7 +172,8 @@ def test_syev_two_launch_tridiagonalisation_above_8192():
     assert float((S @ Z - Z * lam).abs().max()) <= 1e-12 * nrm * grow
 
 
-@pytest.mark.parametrize("n", [40, 300])   # one diagonal tile; 3 x 3 tiles, ragged
+# one diagonal tile; 3 x 3 tiles, ragged; 2 x 2 whole tiles (the LDS-DMA Gram product)
+@pytest.mark.parametrize("n", [40, 300, 256])
 def test_rotate_and_project(n):
     torch, P = require_gpu()
     Hc, Hb, X = make_case(8, 3, n, seed=5)
