@@ -118,7 +118,7 @@ def issued_flops(H, prec):
 
 
 def mixed_precision_report(P, torch, ip, ix, d, cfg, H64, Xb64, keep_frac=1800 / 2048, reps=3,
-                           m_late=(4, 8)):
+                           m_late=(4, 18)):
     """Low-precision filters followed by the FP64 Rayleigh-Ritz with FP64 H,
     against the FP64 pipeline from the same start block (the FP64 pipeline is
     itself checked against the oracle at this size by the tests): FP32 tiles;
@@ -406,6 +406,8 @@ def main():
     ap.add_argument("--max-passes", type=int, default=40)
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the reduced-precision filters and their Ritz-value errors")
+    ap.add_argument("--m-late", default="4,18",
+                    help="comma-separated counts of late FP32 / bf16x3 steps of the precision schedules")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint report (forward and backward on the adjoint workload)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -548,7 +550,8 @@ def main():
         del rr_work, work
         rr_out.clear()
         torch.cuda.empty_cache()
-        out["mixed_vs_f64"] = mixed_precision_report(P, torch, ip, ix, d, cfg, H, Xb)
+        out["mixed_vs_f64"] = mixed_precision_report(
+            P, torch, ip, ix, d, cfg, H, Xb, m_late=tuple(int(v) for v in args.m_late.split(",") if v))
     if not args.no_cpu_baseline:
         import oracle
         log("CPU baseline (oracle) ...")
