@@ -86,7 +86,7 @@ def cpu_baseline(Hc, X, cfg, n_cols, threads=None):
 
 
 STEP_KERNEL = {"f64": "cheb_step_mfma<double>", "f32": "cheb_step_mfma<float>",
-               "bf16": "cheb_step_bf16<float, false>", "bf16x3": "cheb_step_bf16<float, true>"}
+               "bf16": "cheb_step_bf16_patch<float, false>", "bf16x3": "cheb_step_bf16_patch<float, true>"}
 
 
 def step_roofline(prec, alg_flops, alg_bytes, launch_s, traffic=None):
@@ -327,8 +327,7 @@ def run_large(args, P, torch, workload):
                    "m": cfg.m, "h": cfg.h, "nnz": len(d), "tiles": H64.n_tiles,
                    "step": "one ChFSI pass: filter + FP64 Rayleigh-Ritz, bounds from the previous pass"},
         "passes": recs,
-        "roofline": {"bound": "mfma", "kernel": "cheb_step_mfma<float>" if prec == "f32" else
-                     "cheb_step_bf16_pipe<float>", "achieved": round(2.0 * len(d) * cfg.n / launch_s / 1e12, 3),
+        "roofline": {"bound": "mfma", "kernel": STEP_KERNEL[prec], "achieved": round(2.0 * len(d) * cfg.n / launch_s / 1e12, 3),
                      "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                      "frac": round(2.0 * len(d) * cfg.n / launch_s / 1e12 / PEAK_TFLOPS[prec], 4),
                      "traffic": None},
