@@ -76,12 +76,20 @@ def cpu_baseline(Hc, X, cfg, n_cols, threads=None):
         list(ex.map(run, range(threads)))
     dtn = time.perf_counter() - t0
     flops1 = 2.0 * Hc.nnz * n_cols * cfg.m
+    # the same definition in plain C with OpenMP, threads x n_cols-column blocks
+    Xc = np.ascontiguousarray(X[:, :threads * n_cols])
+    t0 = time.perf_counter()
+    oracle.cheb_filter_c(Hc, Xc, cfg.m, cfg.a, cfg.b, cfg.a0, threads=threads, blk=n_cols)
+    dtc = time.perf_counter() - t0
     return {"value": flops1 * threads / dtn / 1e9, "unit": "GFLOP/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{threads * n_cols} of {cfg.n} columns as {threads} threads x {n_cols} columns, "
                       f"full m={cfg.m} filter, SciPy CSR FP64 ({dtn:.1f} s); algorithmic flops "
                       f"2*nnz*cols*m",
             "one_core": {"value": flops1 / dt1 / 1e9, "sample": f"{n_cols} columns ({dt1:.1f} s)"},
+            "c_openmp": {"value": flops1 * threads / dtc / 1e9, "cores": threads,
+                         "sample": f"the same {threads * n_cols} columns by the C/OpenMP oracle "
+                                   f"(CSR FP64, {n_cols}-column blocks, {dtc:.1f} s)"},
             "host_cpus": os.cpu_count(), "host": platform.processor() or platform.machine()}
 
 

@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
 leg of the benchmark may import this package.  It shares no code with the GPU
 library and the GPU library never calls it.
 
-Everything here is plain, slow and FP64 (NumPy / SciPy on the CPU).  Where the
+Everything here is plain, slow and FP64 (NumPy / SciPy on the CPU, and the
+filter once more in plain C with OpenMP, cheb_filter.c, for the CPU baseline).  Where the
 method reaches a result that has a plain definition (the filter is a fixed
 polynomial of H applied to X; the Ritz pairs of H on a subspace), the oracle
 computes that definition; where it does not (Cholesky-QR as an algorithm), the
@@ -29,3 +30,4 @@ from .chfsi import (  # noqa: F401
     density_matrix_on_pattern,
     electron_density,
 )
+from .cfilter import cheb_filter_c  # noqa: F401  (C/OpenMP form of cheb_filter)

@@ -85,6 +85,40 @@ def test_filter_matches_spectral_closed_form(r, h, m):
         assert np.linalg.norm(Y - ref) / np.linalg.norm(ref) < 1e-13
 
 
+# The C/OpenMP oracle (oracle/cheb_filter.c) computes the same definition; it is
+# pinned on its own to the spectral closed form, and checked on the special cases
+# that exercise its column blocks (a ragged last block, one column, blocks wider
+# than the matrix) and its thread split.
+@pytest.mark.parametrize("r,h,m,n,blk,threads", [(4, 1, 1, 3, 8, 1), (4, 3, 10, 7, 3, 2),
+                                                 (5, 2, 7, 9, 4, 3), (6, 2, 16, 1, 8, 4),
+                                                 (6, 3, 20, 17, 64, 2)])
+def test_c_oracle_filter_matches_spectral_closed_form(r, h, m, n, blk, threads):
+    H, N = small_h(r, h)
+    lam, V = np.linalg.eigh(H.toarray())
+    X = workload.gaussian_block(N, n, 7)
+    Y = oracle.cheb_filter_c(H, X, m, A, B, A0, threads=threads, blk=blk)
+    ref = V @ (p_of(lam, m)[:, None] * (V.T @ X))
+    assert np.linalg.norm(Y - ref) / np.linalg.norm(ref) <= 1e-12
+
+
+def test_c_oracle_filter_special_cases():
+    # m = 1: (H - cI) X / (a0 - c); H = c I: cos(m pi / 2) / T_m(tau) X
+    H, N = small_h(4, 2)
+    X = workload.gaussian_block(N, 5, 3)
+    e, c, tau = oracle.filter_parameters(A, B, A0)
+    Y1 = oracle.cheb_filter_c(H, X, 1, A, B, A0)
+    assert np.allclose(Y1, (H @ X - c * X) / (A0 - c), rtol=0, atol=1e-13 * np.abs(X).max())
+    Hc = sp.identity(N, format="csr") * c
+    for m in (3, 4, 10):
+        Y = oracle.cheb_filter_c(Hc, X, m, A, B, A0)
+        assert np.allclose(Y, np.cos(m * np.pi / 2) / t_closed(m, np.array([tau]))[0] * X,
+                           rtol=0, atol=1e-15)
+    with pytest.raises(ValueError):
+        oracle.cheb_filter_c(H, X, 0, A, B, A0)
+    with pytest.raises(ValueError):
+        oracle.cheb_filter_c(H, X, 5, A, A, A0)
+
+
 def test_filter_config1_scaled_vs_definition():
     ip, ix, d, N = workload.lattice_hamiltonian(20, 3, 0)
     H = oracle.csr_from_arrays(ip, ix, d, N)
