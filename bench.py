@@ -35,12 +35,12 @@ PEAK_HBM_GBS = 8000.0
 # see profiles/cheb_step_<precision>_lattice60_h4_n2048_m20_bytes.md.  Valid only while
 # the kernel source is the one that was profiled.
 COUNTED_TRAFFIC = {
-    ("f64", "lattice60_h4_n2048_m20"): {"read_bytes": 90.968e9, "write_bytes": 3.539e9,
-                                        "kernel_sha256_16": "6ae90bb0da36856c"},
-    ("bf16", "lattice60_h4_n2048_m20"): {"read_bytes": 16.195e9, "write_bytes": 1.774e9,
-                                        "kernel_sha256_16": "6ae90bb0da36856c"},
-    ("bf16x3", "lattice60_h4_n2048_m20"): {"read_bytes": 16.964e9, "write_bytes": 1.772e9,
-                                        "kernel_sha256_16": "6ae90bb0da36856c"},
+    ("f64", "lattice60_h4_n2048_m20"): {"read_bytes": 90.830e9, "write_bytes": 3.539e9,
+                                        "kernel_sha256_16": "817772aa93261775"},
+    ("bf16", "lattice60_h4_n2048_m20"): {"read_bytes": 16.200e9, "write_bytes": 1.774e9,
+                                        "kernel_sha256_16": "817772aa93261775"},
+    ("bf16x3", "lattice60_h4_n2048_m20"): {"read_bytes": 16.957e9, "write_bytes": 1.772e9,
+                                        "kernel_sha256_16": "817772aa93261775"},
 }
 
 

@@ -8,12 +8,13 @@
 // contracted on the matrix cores and the recurrence update is applied in the
 // epilogue, so Yk, Yprev and Yout each cross HBM once per step.
 //
-// Work decomposition: one work-group owns one block row B and one column tile
-// of vectors and walks the (at most 27) tiles of B, accumulating in matrix-core
-// registers.  Each output element is produced by exactly one work-group, so
-// results are deterministic (no atomics).  FP64 and FP32 tiles use
-// cheb_step_mfma<T> (16x16x4 ops, tiles moved to LDS by LDS-DMA); BF16 tiles
-// use cheb_step_bf16_pipe (16x16x32 bf16 ops).
+// Work decomposition: FP64 and FP32 tiles use cheb_step_mfma<T> (16x16x4 ops):
+// one work-group owns one block row B and one column tile of vectors and walks
+// the (at most 27) tiles of B, accumulating in matrix-core registers, the tiles
+// moved to LDS by LDS-DMA.  BF16 tiles use cheb_step_bf16_patch (16x16x32 bf16
+// ops): one work-group owns a 2x2x2 patch of block rows and walks the union of
+// their tile columns.  Each output element is produced by exactly one
+// work-group, so results are deterministic (no atomics).
 //
 // Tile values are stored in matrix-core fragment order: element (i, j) of a
 // tile at 64*(4*(j/4) + i/16) + 16*(j%4) + i%16, i.e. the 16x4 fragment
@@ -27,8 +28,6 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-
-
 
 // MFMA 16x16x4 on scalar operands: lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // output item t of lane l is D[row(l, t)][l%16].
@@ -267,8 +266,11 @@ template <> __device__ inline __bf16 buffer_load<__bf16>(__amdgpu_buffer_rsrc_t 
 // columns (4x4x4 = 64 blocks for a patch at h <= 4, against 8 x 27 tiles) is
 // built in LDS at the start, and each neighbouring Y_k panel is read once per
 // union step and contracted with every patch row's tile in that block column.
-// The BF16 step is bound by bytes, and the panels (not the 4x smaller tiles)
-// are most of them: this cuts the panel reads by 27*8/64.
+// The panels (not the 4x smaller tiles) are most of the step's bytes: this cuts
+// the panel reads by 27*8/64 (41 -> 16 GB read beyond L2 per launch at the
+// full-size workload).  What bounds the step then is the instruction stream of
+// each union step (schedule, slot and count bookkeeping, waits) on two waves
+// per SIMD that meet at one barrier, not the bytes.
 //  - A (H tiles, 16x32 fragment order) moved to LDS by LDS-DMA through a ring
 //    of HS tile slots, as far ahead as the ring allows;
 //  - B (Y_k panel): FP32 iterates moved to LDS by buffer LDS-DMA (range-checked
@@ -292,9 +294,9 @@ template <> __device__ inline __bf16 buffer_load<__bf16>(__amdgpu_buffer_rsrc_t 
 // walked one block row at a time in chunks of PB_CAP tiles.
 constexpr int PB_R = 8, PB_WAVES = 8, PB_THREADS = 64 * PB_WAVES, PB_NV = 16 * PB_WAVES;
 // launch order of the patch kernel: column groups of PB_CGROUP column tiles
-// outermost; each XCD takes runs of PB_RUN consecutive patches (all column tiles
-// of the group), so that neighbouring patches, which share half of their
-// neighbour panels, run on one XCD at the same time
+// outermost; each XCD takes runs of PB_RUN consecutive patches with all column
+// tiles of the group (runs of 2, 4 or 8 neighbouring patches, which share half
+// of their neighbour panels, with 16, 8 or 4 column tiles, measured no faster)
 constexpr int PB_CGROUP = 16, PB_RUN = 1;
 constexpr int PB_CAP = 27 * PB_R;
 constexpr int PB_YS = 2;                 // Y panel ring stages
