@@ -138,6 +138,7 @@ __global__ __launch_bounds__(256) void rank2_fused_kernel(double *A, int64_t n, 
 }
 
 constexpr int RB = 8;   // row elements loaded together in tridiag_step_kernel
+constexpr int64_t kTridiagTwoRows = 1024;   // trailing rows from which a wave takes two rows
 
 // Step k's rank-2 update fused with step k+1's reflector and product, so that
 // the trailing block is read and written once per step.  Row k+1 (row 0 of the
@@ -149,14 +150,19 @@ constexpr int RB = 8;   // row elements loaded together in tridiag_step_kernel
 // which no later step reads, is left as it is.  p and pv of step k are read
 // and those of step k+1 written to separate buffers.  The arithmetic and the
 // summation order are those of house_symv_kernel and rank2_fused_kernel.
+// RW rows of the step-(k+1) block per wave (RW = 2 for large blocks: p and v are
+// loaded once for both rows, and the work-group's own reflector is formed for
+// twice the rows); nparts = the number of partial sums pv written by the launch
+// before (one per work-group)
+template <int RW>
 __global__ __launch_bounds__(256) void tridiag_step_kernel(double *A, int64_t n, int64_t k,
                                                            double *V, double *tau, double *d,
                                                            double *e, const double *p,
-                                                           const double *pv, double *p1,
-                                                           double *pv1, int *nonfinite) {
+                                                           const double *pv, int64_t nparts,
+                                                           double *p1, double *pv1, int *nonfinite) {
   extern __shared__ double vn[];
   __shared__ double red[4], part[4];
-  const int64_t m = n - k - 1, m1 = m - 1, nparts = (m + 3) / 4;
+  const int64_t m = n - k - 1, m1 = m - 1;
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < nparts; i += 256) s += pv[i];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
@@ -201,36 +207,53 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(double *A, int64_t n,
     }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t r = (int64_t)blockIdx.x * 4 + wv;      // row of the step-(k+1) block
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * RW;   // first row of the step-(k+1) block
   double pvr = 0.0;
-  if (r < m1) {
-    const int64_t i = r + 1;                           // its row in the step-k block
-    const double vi = v[i], wi = p[i] - K * vi;
-    double *row = A + (k + 1 + i) * n + k + 1;
-    double acc = 0.0;
+  if (r0 < m1) {
+    const int nr = (int)min<int64_t>(RW, m1 - r0);         // rows of this wave (wave-uniform)
+    double vi[RW], wi[RW], acc[RW];
+    double *row[RW];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      const int64_t i = min<int64_t>(r0 + q, m1 - 1) + 1;  // its row in the step-k block
+      vi[q] = v[i];
+      wi[q] = p[i] - K * vi[q];
+      row[q] = A + (k + 1 + i) * n + k + 1;
+      acc[q] = 0.0;
+    }
     for (int64_t j0 = 1 + lane; j0 < m; j0 += 64 * RB) {
-      double aj[RB], pj[RB], vj[RB];
+      double aj[RW][RB], pj[RB], vj[RB];
 #pragma unroll
       for (int t = 0; t < RB; ++t) {
         const int64_t j = min(j0 + 64 * t, m - 1);
-        aj[t] = row[j];
         pj[t] = p[j];
         vj[t] = v[j];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) aj[q][t] = row[q][j];
       }
 #pragma unroll
-      for (int t = 0; t < RB; ++t) {
-        const int64_t j = j0 + 64 * t;
-        if (j < m) {
-          const double a = aj[t] - (vi * (pj[t] - K * vj[t]) + wi * vj[t]);
-          row[j] = a;
-          acc += a * vn[j - 1];
+      for (int q = 0; q < RW; ++q) {
+        if (q >= nr) break;
+#pragma unroll
+        for (int t = 0; t < RB; ++t) {
+          const int64_t j = j0 + 64 * t;
+          if (j < m) {
+            const double a = aj[q][t] - (vi[q] * (pj[t] - K * vj[t]) + wi[q] * vj[t]);
+            row[q][j] = a;
+            acc[q] += a * vn[j - 1];
+          }
         }
       }
     }
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-    const double pi = t * acc;
-    pvr = pi * vn[r];
-    if (lane == 0) p1[r] = pi;
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      if (q >= nr) break;
+      double s = acc[q];
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+      const double pi = t * s;
+      pvr += pi * vn[r0 + q];
+      if (lane == 0) p1[r0 + q] = pi;
+    }
   }
   if (lane == 0) part[wv] = pvr;
   __syncthreads();
@@ -597,11 +620,22 @@ hipError_t run_syev(int64_t n, const double *Ain, int64_t lda, double *lambda, d
       hipLaunchKernelGGL(house_symv_kernel, dim3((unsigned)((n + 2) / 4)), dim3(256), 0, s, A, n,
                          (int64_t)0, V, tau, d, e, pb[0], pvb[0], info + 1);
     int cur = 0;
+    int64_t nparts = (n + 2) / 4;                      // partial sums of the launch before
     for (int64_t k = 0; k + 3 < n; ++k, cur ^= 1) {
       const int64_t m1 = n - k - 2;
-      hipLaunchKernelGGL(tridiag_step_kernel, dim3((unsigned)((m1 + 3) / 4)), dim3(256),
-                         (unsigned)(m1 * sizeof(double)), s, A, n, k, V, tau, d, e, pb[cur],
-                         pvb[cur], pb[cur ^ 1], pvb[cur ^ 1], info + 1);
+      if (m1 >= kTridiagTwoRows) {
+        const int64_t g = (m1 + 7) / 8;
+        hipLaunchKernelGGL(tridiag_step_kernel<2>, dim3((unsigned)g), dim3(256),
+                           (unsigned)(m1 * sizeof(double)), s, A, n, k, V, tau, d, e, pb[cur],
+                           pvb[cur], nparts, pb[cur ^ 1], pvb[cur ^ 1], info + 1);
+        nparts = g;
+      } else {
+        const int64_t g = (m1 + 3) / 4;
+        hipLaunchKernelGGL(tridiag_step_kernel<1>, dim3((unsigned)g), dim3(256),
+                           (unsigned)(m1 * sizeof(double)), s, A, n, k, V, tau, d, e, pb[cur],
+                           pvb[cur], nparts, pb[cur ^ 1], pvb[cur ^ 1], info + 1);
+        nparts = g;
+      }
     }
     if (n > 2)
       hipLaunchKernelGGL(rank2_fused_kernel, dim3((unsigned)((2 + 3) / 4)), dim3(256), 0, s, A, n,
