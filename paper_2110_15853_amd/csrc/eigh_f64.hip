@@ -496,28 +496,39 @@ __global__ __launch_bounds__(256) void wy_vblock_kernel(const double *V, int64_t
   }
 }
 
-// G[i][j] = v_i . v_j for i < j (one wave per pair)
-__global__ __launch_bounds__(256) void wy_gram_kernel(const double *Vb, int64_t n, int64_t k0,
-                                                      int nb, double *G) {
+// G_b[i][j] = v_{k0+i} . v_{k0+j} (i < j) for every block b of WY_NB reflectors
+// (k0 = b WY_NB), straight from the rows of V (one wave per pair, grid.y = block;
+// v_k is zero up to row k, so the sum runs over rows past k0 + j)
+__global__ __launch_bounds__(256) void wy_gram_all_kernel(const double *V, int64_t n, int64_t R,
+                                                          double *G) {
+  const int64_t b = blockIdx.y, k0 = b * WY_NB;
+  const int nb = (int)min<int64_t>(WY_NB, R - k0);
   const int pair = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (pair >= nb * nb) return;
   const int i = pair / nb, j = pair % nb;
   if (i >= j) return;
+  const double *vi = V + (k0 + i) * n, *vj = V + (k0 + j) * n;
   double s = 0.0;
-  for (int64_t x = k0 + 1 + j + lane; x < n; x += 64) s += Vb[x * nb + i] * Vb[x * nb + j];
+  for (int64_t x = k0 + 1 + j + lane; x < n; x += 64) s += vi[x] * vj[x];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-  if (lane == 0) G[i * nb + j] = s;
+  if (lane == 0) G[b * WY_NB * WY_NB + i * nb + j] = s;
 }
 
-// T from G and tau (one work-group, nb <= 64), in LDS
-__global__ __launch_bounds__(64) void wy_t_kernel(const double *G, const double *tau, int64_t k0,
-                                                  int nb, double *T) {
+// compact-WY factor T_b of every block (one work-group per block, nb <= 64, in
+// LDS): T[j][j] = tau_j and T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j], the operands
+// of 8 terms read before any is used (one LDS latency per 8)
+__global__ __launch_bounds__(64) void wy_t_all_kernel(const double *G, const double *tau, int64_t R,
+                                                      double *T) {
   __shared__ double sT[64][65], sG[64][65];
+  const int64_t b = blockIdx.x, k0 = b * WY_NB;
+  const int nb = (int)min<int64_t>(WY_NB, R - k0);
+  const double *Gb = G + b * WY_NB * WY_NB;
+  double *Tb = T + b * WY_NB * WY_NB;
   const int i = threadIdx.x;
   for (int j = 0; j < nb; ++j) {
     if (i < nb) {
       sT[i][j] = 0.0;
-      sG[i][j] = i < j ? G[i * nb + j] : 0.0;
+      sG[i][j] = i < j ? Gb[i * nb + j] : 0.0;
     }
   }
   __syncthreads();
@@ -525,8 +536,6 @@ __global__ __launch_bounds__(64) void wy_t_kernel(const double *G, const double 
     const double tj = tau[k0 + j];
     double s = 0.0;
     if (i < j) {
-      // operands of 8 terms are read before any is used (one LDS latency per 8);
-      // terms past j - 1 read in-range entries and are masked out
       for (int l0 = i; l0 < j; l0 += 8) {
         double a[8], g[8];
 #pragma unroll
@@ -546,7 +555,7 @@ __global__ __launch_bounds__(64) void wy_t_kernel(const double *G, const double 
     __syncthreads();
   }
   for (int j = 0; j < nb; ++j)
-    if (i < nb) T[i * nb + j] = sT[i][j];
+    if (i < nb) Tb[i * nb + j] = sT[i][j];
 }
 
 __global__ void clear_ints_kernel(int *p, int count) {
@@ -560,7 +569,7 @@ inline unsigned grid_for(int64_t work) {
 
 struct SyevLayout {
   int64_t n, np, splits;
-  size_t a, dg, du, du2, dl, swp, zt, z2, g, m, chol, partial, vec, info, wy, total;
+  size_t a, dg, du, du2, dl, swp, zt, z2, g, m, chol, partial, vec, info, wy, wyt, total;
 };
 
 SyevLayout syev_layout(int64_t n) {
@@ -582,6 +591,7 @@ SyevLayout syev_layout(int64_t n) {
   L.vec = take(8 * (size_t)n + 8);
   L.info = take(4);
   L.wy = take(3 * (size_t)WY_NB * n + 2 * (size_t)WY_NB * WY_NB);
+  L.wyt = take(2 * (size_t)((n + WY_NB - 1) / WY_NB) * WY_NB * WY_NB);   // G and T of every block
   L.total = off;
   return L;
 }
@@ -672,14 +682,21 @@ hipError_t run_syev(int64_t n, const double *Ain, int64_t lda, double *lambda, d
   {
     const int64_t R = n - 2;                        // reflectors k = 0 .. n-3
     double *Vb = (double *)(w + L.wy), *W = Vb + (int64_t)WY_NB * n, *W2 = Vb + 2 * (int64_t)WY_NB * n;
-    double *Gw = Vb + 3 * (int64_t)WY_NB * n, *Tw = Gw + WY_NB * WY_NB;
     double *wpart = partial;                        // split-K partials of W (free here)
+    // the T factors of all blocks first (they depend only on V and tau): a few
+    // launches instead of a sequence of single-work-group ones
+    const int64_t nblk = (R + WY_NB - 1) / WY_NB;
+    double *Gall = (double *)(w + L.wyt), *Tall = Gall + nblk * WY_NB * WY_NB;
+    if (nblk > 0) {
+      hipLaunchKernelGGL(wy_gram_all_kernel, dim3((unsigned)((WY_NB * WY_NB + 3) / 4), (unsigned)nblk),
+                         dim3(256), 0, s, V, n, R, Gall);
+      hipLaunchKernelGGL(wy_t_all_kernel, dim3((unsigned)nblk), dim3(64), 0, s, Gall, tau, R, Tall);
+    }
     for (int64_t k0 = (R > 0 ? (R - 1) / WY_NB * WY_NB : -1); k0 >= 0; k0 -= WY_NB) {
       const int nb = (int)std::min<int64_t>(WY_NB, R - k0);
       const int64_t m = n - k0 - 1;                 // rows touched
+      const double *Tw = Tall + (k0 / WY_NB) * WY_NB * WY_NB;
       hipLaunchKernelGGL(wy_vblock_kernel, dim3(grid_for((int64_t)nb * n)), dim3(256), 0, s, V, n, k0, nb, Vb);
-      hipLaunchKernelGGL(wy_gram_kernel, dim3((unsigned)((nb * nb + 3) / 4)), dim3(256), 0, s, Vb, n, k0, nb, Gw);
-      hipLaunchKernelGGL(wy_t_kernel, dim3(1), dim3(64), 0, s, Gw, tau, k0, nb, Tw);
       // W = V^T Z[k0+1:, :]   (nb x n), split over the m rows
       const int ws = (int)std::max<int64_t>(1, std::min<int64_t>(16, m / 128));
       if ((err = launch_gemm_tn_general(Vb + (k0 + 1) * nb, nb, Z + (k0 + 1) * ldz, ldz, m, nb, n, W,
