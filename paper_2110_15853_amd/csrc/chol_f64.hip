@@ -13,6 +13,8 @@
 // matrix-core products (ranges of 1, 2, 4, ... blocks).  Breakdown (a
 // non-positive or non-finite pivot) sets *info and the factorisation kernels
 // return immediately.
+#include <utility>
+
 #include "ttdft_internal.h"
 
 namespace ttdft {
@@ -75,82 +77,138 @@ __global__ void gram_scale_kernel(double *G, int64_t n, int64_t np, const double
   }
 }
 
-// Factor the diagonal block p with four waves; write L_pp (lower) into G and
-// L_pp^{-1} into X.  The block sits in LDS row-major, lane i of every wave on
-// row i.  Step j (a rolled loop): lanes i > j of wave 0 form l_ij = a_ij /
-// sqrt(a_jj) in place; after a barrier every wave applies a_ik -= l_ij l_kj to
-// the columns k > j it owns (wave w: columns 16w .. 16w+15), l_kj read with the
-// same address by every lane, and a second barrier closes the step.  Then wave 0
-// has lane c hold column c of the identity in registers and eliminate with the
-// factor's columns: x_j = b_j / l_jj, b_k -= l_kj x_j (k > j), leaving column c
-// of L^{-1} (unrolled; a scheduling barrier between steps bounds the register
-// use).
+// the value `v` of lane `src` in every lane (src wave-uniform)
+__device__ inline double lane_value(double v, int src) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+constexpr int PW = 16;   // panel width of the diagonal-block factorisation
+
+// column step J of a panel (columns c0 .. c0+PW-1) factored by one wave: lane i
+// holds row i of the panel in a[]; the pivot and the multipliers L[c0+k][c0+J]
+// reach every lane by readlane (rows above the panel update entries above the
+// diagonal, which are never read)
+template <int J>
+__device__ __forceinline__ void panel_column(double (&a)[PW], int lane, int c0, int p, int &bad) {
+  double piv = lane_value(a[J], c0 + J);
+  if (!(piv > 0.0) || !isfinite(piv)) {
+    if (!bad) bad = p * T + c0 + J + 1;
+    piv = 1.0;
+  }
+  const double ljj = sqrt(piv);
+  a[J] = lane > c0 + J ? a[J] / ljj : (lane == c0 + J ? ljj : a[J]);
+#pragma unroll
+  for (int k = J + 1; k < PW; ++k) a[k] = fma(-a[J], lane_value(a[J], c0 + k), a[k]);
+}
+template <int... J>
+__device__ __forceinline__ void panel_columns(std::integer_sequence<int, J...>, double (&a)[PW],
+                                              int lane, int c0, int p, int &bad) {
+  (panel_column<J>(a, lane, c0, p, bad), ...);
+}
+
+// Factor the diagonal block p with four waves; write L_pp (lower, zeros above)
+// into G and L_pp^{-1} into X.  The block sits in LDS row-major.
+//  - factorisation in panels of PW columns: wave 0 factors a panel with row i in
+//    lane i's registers (no barrier inside the panel), then all four waves apply
+//    the panel's rank-PW update to the lower triangle of the trailing block (two
+//    barriers per panel);
+//  - inverse by blocks: the four 16x16 diagonal blocks are inverted by forward
+//    substitution, one per wave, then the coupling blocks of the inverse of
+//    [[L11, 0], [L21, L22]] follow as X21 = -X22 (L21 X11), first for the two
+//    32x32 halves, then for the whole block.
 __global__ __launch_bounds__(256) void potrf_diag_kernel(double *G, int64_t np, int p, double *X,
                                                          int *info) {
   if (*info) return;
-  __shared__ double La[T][T + 1];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ double La[T][T + 1], sX[T][T + 1], sW[T][T + 1];
+  __shared__ int s_bad;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double *Gp = G + (int64_t)p * T * np + (int64_t)p * T;
-  for (int r = wv; r < T; r += 4) La[r][lane] = Gp[r * np + lane];   // coalesced rows
+  for (int r = wv; r < T; r += 4) {
+    La[r][lane] = Gp[r * np + lane];   // coalesced rows
+    sX[r][lane] = 0.0;
+  }
+  if (tid == 0) s_bad = 0;
   __syncthreads();
-  int bad = 0;
-  for (int j = 0; j < T; ++j) {
-    double piv = La[j][j];                  // the same value in every lane
-    if (!(piv > 0.0) || !isfinite(piv)) {
-      if (!bad) bad = p * T + j + 1;
-      piv = 1.0;
-    }
-    const double ljj = sqrt(piv);
+  for (int c0 = 0; c0 < T; c0 += PW) {
     if (wv == 0) {
-      if (lane > j) La[lane][j] = La[lane][j] / ljj;
-      if (lane == j) La[j][j] = ljj;
+      double a[PW];
+#pragma unroll
+      for (int k = 0; k < PW; ++k) a[k] = La[lane][c0 + k];
+      int bad = 0;
+      panel_columns(std::make_integer_sequence<int, PW>{}, a, lane, c0, p, bad);
+#pragma unroll
+      for (int k = 0; k < PW; ++k) La[lane][c0 + k] = a[k];
+      if (lane == 0 && bad && !s_bad) s_bad = bad;
     }
     __syncthreads();
-    // trailing update of this wave's 16 columns in chunks of 8: all reads of a
-    // chunk, then the products (kept only for columns k > j; entries above the
-    // diagonal are updated too but never read), then the writes
-    const double l = lane > j ? La[lane][j] : 0.0;
-    for (int kc = max(16 * wv, (j + 1) & ~7); kc < 16 * wv + 16; kc += 8) {
-      double lk[8], ak[8];
+    // rank-PW update of the lower triangle of the trailing block: row i in lane
+    // i, columns t0 + wv, t0 + wv + 4, ... <= i
+    const int t0 = c0 + PW, i = lane;
+    if (i >= t0) {
+      double li[PW];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        lk[u] = La[kc + u][j];
-        ak[u] = La[lane][kc + u];
+      for (int j = 0; j < PW; ++j) li[j] = La[i][c0 + j];
+      for (int k = t0 + wv; k <= i; k += 4) {
+        double s = La[i][k];
+#pragma unroll
+        for (int j = 0; j < PW; ++j) s = fma(-li[j], La[k][c0 + j], s);
+        La[i][k] = s;
       }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const double v = fma(-l, lk[u], ak[u]);
-        ak[u] = kc + u > j ? v : ak[u];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) La[lane][kc + u] = ak[u];
     }
     __syncthreads();
   }
+  const int bad = s_bad;
   if (bad) {
-    if (threadIdx.x == 0) atomicCAS(info, 0, bad);
+    if (tid == 0) atomicCAS(info, 0, bad);
     return;
   }
-  if (wv == 0) {
-    double b[T];
+  // inverse of the four 16x16 diagonal blocks, block wv in wave wv, lane = column
+  if (lane < 16) {
+    const int o = 16 * wv;
+    double b[16];
 #pragma unroll
-    for (int k = 0; k < T; ++k) b[k] = k == lane ? 1.0 : 0.0;
+    for (int k = 0; k < 16; ++k) b[k] = k == lane ? 1.0 : 0.0;
 #pragma unroll
-    for (int j = 0; j < T; ++j) {
-      const double x = b[j] / La[j][j];
+    for (int j = 0; j < 16; ++j) {
+      const double x = b[j] / La[o + j][o + j];
       b[j] = x;
 #pragma unroll
-      for (int k = j + 1; k < T; ++k) b[k] = fma(-La[k][j], x, b[k]);
-      __builtin_amdgcn_sched_barrier(0);
+      for (int k = j + 1; k < 16; ++k) b[k] = fma(-La[o + k][o + j], x, b[k]);
     }
-    double *Xp = X + (int64_t)p * T * np + (int64_t)p * T;
 #pragma unroll
-    for (int i = 0; i < T; ++i) Xp[(int64_t)i * np + lane] = b[i];   // lane = column: coalesced
+    for (int k = 0; k < 16; ++k) sX[o + k][o + lane] = b[k];
   }
-  for (int r = wv; r < T; r += 4) Gp[r * np + lane] = lane <= r ? La[r][lane] : 0.0;
+  __syncthreads();
+  // coupling blocks: halves of S = 16 (blocks (0,1) and (2,3)), then S = 32
+  for (int S = 16; S < T; S *= 2) {
+    const int pairs = T / (2 * S), per = S * S;            // entries of one coupling block
+    // W = L21 X11 (X11 lower: terms m >= c)
+    for (int e = tid; e < pairs * per; e += 256) {
+      const int q = e / per, r = (e % per) / S, c = e % S, o = 2 * S * q;
+      double w = 0.0;
+      for (int m = c; m < S; ++m) w = fma(La[o + S + r][o + m], sX[o + m][o + c], w);
+      sW[o + S + r][o + c] = w;
+    }
+    __syncthreads();
+    // X21 = -X22 W (X22 lower: terms m <= r)
+    for (int e = tid; e < pairs * per; e += 256) {
+      const int q = e / per, r = (e % per) / S, c = e % S, o = 2 * S * q;
+      double x = 0.0;
+      for (int m = 0; m <= r; ++m) x = fma(sX[o + S + r][o + S + m], sW[o + S + m][o + c], x);
+      sX[o + S + r][o + c] = -x;
+    }
+    __syncthreads();
+  }
+  double *Xp = X + (int64_t)p * T * np + (int64_t)p * T;
+  for (int r = wv; r < T; r += 4) {
+    Xp[(int64_t)r * np + lane] = sX[r][lane];               // lane = column: coalesced
+    Gp[r * np + lane] = lane <= r ? La[r][lane] : 0.0;
+  }
 }
 
-// L_ip = A_ip L_pp^{-T} for every block row i > p (one work-group each)
 __global__ __launch_bounds__(256) void trsm_panel_kernel(double *G, int64_t np, int p,
                                                          const double *X, const int *info) {
   if (*info) return;
