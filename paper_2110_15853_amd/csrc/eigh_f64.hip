@@ -270,13 +270,22 @@ __global__ void tail_kernel(const double *A, int64_t n, double *d, double *e) {
 }
 
 // number of eigenvalues of T smaller than x (Sturm count of the LDL^T pivots)
+// number of eigenvalues of T below x: the negative pivots of the LDL^T factors
+// of T - xI.  1/q is the hardware reciprocal refined by two Newton steps (full
+// double accuracy; q is kept away from 0 by pivmin), which halves the dependent
+// chain of a step against an IEEE division; only the signs of the pivots count.
+__device__ inline double recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return fma(r, fma(-q, r, 1.0), r);
+}
 __device__ inline int sturm_count(const double *d, const double *e, int64_t n, double x, double pivmin) {
   int cnt = 0;
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   cnt += q < 0.0;
   for (int64_t i = 1; i < n; ++i) {
-    q = (d[i] - x) - e[i - 1] * e[i - 1] / q;
+    q = (d[i] - x) - e[i - 1] * e[i - 1] * recip(q);
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
   }
@@ -363,20 +372,22 @@ __global__ __launch_bounds__(64) void inverse_iteration_kernel(
     const double l = e[i], dn = d[i + 1] - lam, en = i + 2 < n ? e[i + 1] : 0.0;
     if (fabs(g) >= fabs(l)) {
       const double gp = g != 0.0 ? g : tiny;
-      const double f = l / gp;
-      AT(dg, i) = gp; AT(dl, i) = f; AT(du, i) = u; AT(swp, i) = 0.0;
+      const double rg = recip(gp);
+      const double f = l * rg;
+      AT(dg, i) = rg; AT(dl, i) = f; AT(du, i) = u; AT(swp, i) = 0.0;
       if (i + 2 < n) AT(du2, i) = 0.0;
       g = dn - f * u;
       u = en;
     } else {
-      const double f = g / l;
-      AT(dg, i) = l; AT(dl, i) = f; AT(du, i) = dn; AT(swp, i) = 1.0;
+      const double rl = recip(l);
+      const double f = g * rl;
+      AT(dg, i) = rl; AT(dl, i) = f; AT(du, i) = dn; AT(swp, i) = 1.0;
       if (i + 2 < n) AT(du2, i) = en;
       g = u - f * dn;
       u = -f * en;
     }
   }
-  AT(dg, n - 1) = g != 0.0 ? g : tiny;
+  AT(dg, n - 1) = recip(g != 0.0 ? g : tiny);   // dg holds the reciprocal pivots
   double nrm = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     const double s = start_value(i, j);
@@ -448,7 +459,7 @@ __global__ __launch_bounds__(64) void inverse_iteration_kernel(
             double s = y[t];
             if (i + 1 < n) s -= u1[t] * x1;
             if (i + 2 < n) s -= u2[t] * x2;
-            const double xi = s / g[t];
+            const double xi = s * g[t];            // g: reciprocal pivot
             AT(Zt, i) = xi;
             nrm += xi * xi;
             x2 = x1;
