@@ -9,8 +9,9 @@
 // this product with weights 2 f_c and Abar = Yk = Psi).  One work-group owns one tile and sweeps the vector
 // dimension in 16-wide panels, both operands staged transposed in LDS
 // ([vector][row]) so every matrix-core operand read is 16 consecutive values;
-// the panels are double-buffered, the next one loaded into registers while the
-// current one is contracted (one barrier per panel).
+// the panels are double-buffered, the next two (FP64; one for FP32 and BF16)
+// loaded into registers while the current one is contracted (one barrier per
+// panel).
 // FP64 inputs use the f64 16x16x4 op; FP32 and BF16 inputs accumulate in FP32
 // on the f32 16x16x4 op.  Each tile is written by one work-group in a fixed
 // order, so accumulation over the degree steps is deterministic.  A symmetric
@@ -57,28 +58,37 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
   using O = Op<TC>;
   __shared__ TC sA[2][BK][64 + 1];
   __shared__ TC sB[2][BK][64 + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t t = blockIdx.x;
-  // block row of tile t: the last B with rowptr[B] <= t (binary search)
+  // block row of tile t: the last B with rowptr[B] <= t, by a 64-way search (the
+  // 64 lanes test evenly spaced rows and the range shrinks 64-fold per round: two
+  // dependent loads at a few thousand block rows)
   int64_t lo = 0, hi = n_block_rows;
   while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) / 2;
-    if (rowptr[mid] <= t) lo = mid; else hi = mid;
+    const int64_t step = (hi - lo + 63) / 64, p = lo + lane * step;
+    const bool ok = p < hi && rowptr[p] <= t;
+    const uint64_t bal = __ballot(ok);                    // lane 0 (p = lo) always holds
+    const int64_t top = lo + (int64_t)(63 - __clzll(bal)) * step;
+    hi = min(hi, top + step);
+    lo = top;
   }
   const int64_t B = lo, Bc = tcol[t];
   // symmetric product (Abar = Yk): tile (B', B) is the transpose of tile (B, B');
   // the tile with B' > B computes both, the one with B' < B only when its
-  // mirror is not stored
+  // mirror is not stored (the mirror is looked up 64 columns at a time)
   int64_t tm = -1;
   if (sym && Bc != B) {
-    int64_t a = rowptr[Bc], z = rowptr[Bc + 1];
-    while (a < z) {
-      const int64_t mid = (a + z) / 2;
-      if (tcol[mid] < B) a = mid + 1; else z = mid;
+    const int64_t a = rowptr[Bc], z = rowptr[Bc + 1];
+    for (int64_t base = a; base < z; base += 64) {
+      const int64_t idx = base + lane;
+      const uint64_t hit = __ballot(idx < z && tcol[idx] == B);
+      if (hit) {
+        tm = base + __ffsll((unsigned long long)hit) - 1;
+        break;
+      }
     }
-    if (a < rowptr[Bc + 1] && tcol[a] == B) tm = a;
     if (Bc < B && tm >= 0) return;
   }
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const TX *Ar = Abar + B * 64 * lda;
   const TX *Br = Yk + Bc * 64 * ldb;
 
@@ -100,12 +110,13 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
     live = __builtin_amdgcn_readfirstlane(live);        // lane 0 holds the OR of rows 0..15
   }
 
-  // panels of BK vectors, double-buffered in LDS; the next panel is loaded into
-  // registers while the current one is contracted (columns past n_vec read a
-  // clamped, in-range column and are stored as 0)
+  // panels of BK vectors, double-buffered in LDS; FP64 loads two panels ahead
+  // into registers (two register stages), so a panel's loads have two
+  // contractions to arrive (columns past n_vec read a clamped, in-range column
+  // and are stored as 0)
   constexpr int Q = BK * 64 / THREADS;
-  TC ra[Q], rb[Q];
-  auto load = [&](int64_t c0) {
+  TC ra0[Q], rb0[Q], ra1[Q], rb1[Q];
+  auto load = [&](TC *ra, TC *rb, int64_t c0) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int idx = tid + THREADS * q;
@@ -118,7 +129,7 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
       rb[q] = c < n_vec ? bv : TC(0);
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](const TC *ra, const TC *rb, int buf) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int idx = tid + THREADS * q;
@@ -156,17 +167,40 @@ __global__ __launch_bounds__(THREADS) void sddmm_kernel(
       }
     }
   };
-  load(0);
-  store(0);
-  __syncthreads();
-  int buf = 0;
-  for (int64_t c0 = 0; c0 < n_vec; c0 += BK) {
-    const bool more = c0 + BK < n_vec;
-    if (more) load(c0 + BK);
-    contract(buf);
-    if (more) store(buf ^ 1);
+  const int64_t npanel = (n_vec + BK - 1) / BK;
+  if constexpr (sizeof(TC) == 8) {
+    // LDS buffer p % 2 holds panel p while it is contracted; register stage
+    // (p + 1) % 2 holds panel p + 1 and stage p % 2 receives panel p + 2
+    load(ra0, rb0, 0);
+    if (npanel > 1) load(ra1, rb1, BK);
+    store(ra0, rb0, 0);
     __syncthreads();
-    buf ^= 1;
+    for (int64_t p = 0; p < npanel; p += 2) {
+      if (p + 2 < npanel) load(ra0, rb0, (p + 2) * BK);
+      contract(0);
+      if (p + 1 < npanel) store(ra1, rb1, 1);
+      __syncthreads();
+      if (p + 1 >= npanel) break;
+      if (p + 3 < npanel) load(ra1, rb1, (p + 3) * BK);
+      contract(1);
+      if (p + 2 < npanel) store(ra0, rb0, 0);
+      __syncthreads();
+    }
+  } else {
+    // FP32 products: one register stage (the second one costs half the
+    // occupancy, and the loads then bind: measured slower)
+    load(ra0, rb0, 0);
+    store(ra0, rb0, 0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t p = 0; p < npanel; ++p) {
+      const bool more = p + 1 < npanel;
+      if (more) load(ra0, rb0, (p + 1) * BK);
+      contract(buf);
+      if (more) store(ra0, rb0, buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
   }
 
   TC *out = dH + t * kTileElems;
