@@ -219,17 +219,23 @@ def density_report(P, torch, H, lam, psi, cfg):
             times[k].append(ev[i].elapsed_time(ev[j]))
     tr = float((Pv * H.vals).sum())
     want = 2.0 * float((f * lam).sum())
-    # the sampled product issues 2 * 256 * n flop per 16 x 16 block of a stored tile
-    # that holds a pattern entry (the other blocks are skipped)
+    # the sampled product issues 2 * 256 * n flop per 16 x 16 block that holds a
+    # pattern entry (the other blocks are skipped), over the tiles it forms: P is
+    # symmetric, so the tiles (B, B') with B' >= B and those whose mirror is not stored
     m = H.mask.view(H.n_tiles, 4, 16).cpu().numpy().view(np.uint64)
-    rows_or = np.bitwise_or.reduce(m, axis=2)                       # [tile, row block]
+    rowptr = H.tile_rowptr.cpu().numpy()
+    brow = np.repeat(np.arange(H.n_block_rows, dtype=np.int64), np.diff(rowptr))
+    bcol = H.tile_col.cpu().numpy().astype(np.int64)
+    mirrored = np.isin(bcol * H.n_block_rows + brow, brow * H.n_block_rows + bcol)
+    formed = (bcol >= brow) | ~mirrored
+    rows_or = np.bitwise_or.reduce(m[formed], axis=2)               # [formed tile, row block]
     live = sum(int(np.count_nonzero((rows_or >> np.uint64(16 * jb)) & np.uint64(0xFFFF)))
                for jb in range(4))
     dm_s = float(np.median(times["density_matrix_ms"])) / 1e3
     return {"n_electrons": ne, "kT_hartree": P.KT_500K_HARTREE, "mu": mu,
             **{k: round(float(np.median(v)), 3) for k, v in times.items()},
             "density_matrix_issued_tflops": round(2.0 * 256 * cfg.n * live / dm_s / 1e12, 2),
-            "density_matrix_live_blocks": live, "density_matrix_blocks": 16 * H.n_tiles,
+            "density_matrix_live_blocks": live, "density_matrix_blocks": 16 * int(formed.sum()),
             "sum_rho": float(rho.sum()), "trace_PH": tr, "two_sum_f_lambda": want}
 
 
