@@ -239,7 +239,7 @@ def density_report(P, torch, H, lam, psi, cfg):
             "sum_rho": float(rho.sum()), "trace_PH": tr, "two_sum_f_lambda": want}
 
 
-def adjoint_report(P, torch, workload):
+def adjoint_report(P, torch, workload, dtypes=("f64", "f32")):
     """The filter's adjoint on the adjoint workload (r = 40, h = 3, 512 vectors,
     m = 16, loss sum(w * Y) with w ~ N(0,1)): the forward filter and the backward
     with every iterate stored and with a checkpoint every 4 steps, FP64 and FP32,
@@ -252,7 +252,8 @@ def adjoint_report(P, torch, workload):
     W = torch.from_numpy(workload.gaussian_block(N, cfg.n, cfg.seed, stream="W")).cuda()
     H64 = P.bsr_build(ip, ix, d, cfg.r, dtype=torch.float64, device="cuda")
     out = {"workload": cfg.name, "N": N, "n_vec": cfg.n, "m": cfg.m, "nnz": nnz}
-    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+    for name in dtypes:
+        dt = {"f64": torch.float64, "f32": torch.float32}[name]
         H = H64 if dt == torch.float64 else P.bsr_astype(H64, dt)
         Xb, Wb = P.to_blocked(X.to(dt), H), P.to_blocked(W.to(dt), H)
         runs = {
@@ -423,6 +424,9 @@ def main():
                     help="comma-separated counts of late FP32 / bf16x3 steps of the precision schedules")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint report (forward and backward on the adjoint workload)")
+    ap.add_argument("--adjoint-only", default="",
+                    help="run only the adjoint report for these iterate types (e.g. f64 or "
+                         "f64,f32) and print it as one JSON line")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain device copy of the X block (known bytes) before the timed "
                          "steps, to scale hardware byte counters")
@@ -440,6 +444,17 @@ def main():
     import workload
 
     cfg = workload.CONFIGS[args.workload]
+    if args.adjoint_only:
+        if args.calib_copy:                 # known bytes for scaling byte counters
+            a = torch.ones(64000 * 512, dtype=torch.float64, device="cuda")
+            b = torch.empty_like(a)
+            b.copy_(a)
+            torch.cuda.synchronize()
+            log(f"calibration copy: {a.numel() * 8} bytes read and written")
+            del a, b
+        print(json.dumps({"adjoint": adjoint_report(P, torch, workload,
+                                                    tuple(args.adjoint_only.split(",")))}))
+        return
     log(f"workload {cfg}")
     if args.solve:
         run_solve(args, P, torch, workload)
