@@ -163,20 +163,16 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(double *A, int64_t n,
   extern __shared__ double vn[];
   __shared__ double red[4], part[4];
   const int64_t m = n - k - 1, m1 = m - 1;
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < nparts; i += 256) s += pv[i];
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  const double K = 0.5 * tau[k] * (red[0] + red[1] + red[2] + red[3]);
-  __syncthreads();                                     // red is reused below
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double *v = V + k * n + k + 1;                 // reflector k, v[0] = 1
   const double *x = A + (k + 1) * n + k + 1;           // row k+1 before the update
-  const double w0 = p[0] - K * v[0];
-  // The loops over a row load RB elements (clamped into range) before using
-  // any: one memory latency per RB elements rather than per element.
-  for (int64_t j0 = 1 + threadIdx.x; j0 < m; j0 += 256 * RB) {
-    double xj[RB], pj[RB], vj[RB];
+  // Every load that does not depend on the sum of the partials is issued before
+  // it: the first RB elements of row k+1 with p and v (the reflector's inputs)
+  // and the first RB elements of this wave's rows with p and v for them, so that
+  // their latencies overlap.  The loops over a row load RB elements (clamped
+  // into range) before using any: one memory latency per RB elements.
+  double xj[RB], pj[RB], vj[RB];
+  auto load_x = [&](int64_t j0) {
 #pragma unroll
     for (int t = 0; t < RB; ++t) {
       const int64_t j = min(j0 + 256 * t, m - 1);
@@ -184,10 +180,54 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(double *A, int64_t n,
       pj[t] = p[j];
       vj[t] = v[j];
     }
+  };
+  const int64_t jx0 = 1 + threadIdx.x;
+  if (jx0 < m) load_x(jx0);
+  const double p0 = p[0], v0 = v[0], x0 = x[0];
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * RW;   // first row of the step-(k+1) block
+  const bool has_rows = r0 < m1;                            // wave-uniform
+  double vi[RW], pi_[RW], aj[RW][RB], qj[RB], uj[RB];
+  double *row[RW];
+#pragma unroll
+  for (int q = 0; q < RW; ++q) {
+    const int64_t i = min<int64_t>(r0 + q, m1 - 1) + 1;    // its row in the step-k block
+    row[q] = A + (k + 1 + i) * n + k + 1;
+  }
+  auto load_rows = [&](int64_t j0) {
+#pragma unroll
+    for (int t = 0; t < RB; ++t) {
+      const int64_t j = min(j0 + 64 * t, m - 1);
+      qj[t] = p[j];
+      uj[t] = v[j];
+#pragma unroll
+      for (int q = 0; q < RW; ++q) aj[q][t] = row[q][j];
+    }
+  };
+  const int64_t jr0 = 1 + lane;
+  if (has_rows) {
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      const int64_t i = min<int64_t>(r0 + q, m1 - 1) + 1;
+      vi[q] = v[i];
+      pi_[q] = p[i];
+    }
+    if (jr0 < m) load_rows(jr0);
+  }
+
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < nparts; i += 256) s += pv[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (lane == 0) red[wv] = s;
+  __syncthreads();
+  const double K = 0.5 * tau[k] * (red[0] + red[1] + red[2] + red[3]);
+  __syncthreads();                                     // red is reused below
+  const double w0 = p0 - K * v0;
+  for (int64_t j0 = jx0; j0 < m; j0 += 256 * RB) {
+    if (j0 != jx0) load_x(j0);
 #pragma unroll
     for (int t = 0; t < RB; ++t) {
       const int64_t j = j0 + 256 * t;
-      if (j < m) vn[j - 1] = xj[t] - (v[0] * (pj[t] - K * vj[t]) + w0 * vj[t]);
+      if (j < m) vn[j - 1] = xj[t] - (v0 * (pj[t] - K * vj[t]) + w0 * vj[t]);
     }
   }
   __syncthreads();
@@ -202,35 +242,21 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(double *A, int64_t n,
     if (threadIdx.x == 0) {
       if (!isfinite(beta) || !isfinite(t)) atomicExch(nonfinite, 1);
       tau[k + 1] = t;
-      d[k + 1] = x[0] - (v[0] * w0 + w0 * v[0]);
+      d[k + 1] = x0 - (v0 * w0 + w0 * v0);
       e[k + 1] = beta;
     }
   }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * RW;   // first row of the step-(k+1) block
   double pvr = 0.0;
-  if (r0 < m1) {
+  if (has_rows) {
     const int nr = (int)min<int64_t>(RW, m1 - r0);         // rows of this wave (wave-uniform)
-    double vi[RW], wi[RW], acc[RW];
-    double *row[RW];
+    double wi[RW], acc[RW];
 #pragma unroll
     for (int q = 0; q < RW; ++q) {
-      const int64_t i = min<int64_t>(r0 + q, m1 - 1) + 1;  // its row in the step-k block
-      vi[q] = v[i];
-      wi[q] = p[i] - K * vi[q];
-      row[q] = A + (k + 1 + i) * n + k + 1;
+      wi[q] = pi_[q] - K * vi[q];
       acc[q] = 0.0;
     }
-    for (int64_t j0 = 1 + lane; j0 < m; j0 += 64 * RB) {
-      double aj[RW][RB], pj[RB], vj[RB];
-#pragma unroll
-      for (int t = 0; t < RB; ++t) {
-        const int64_t j = min(j0 + 64 * t, m - 1);
-        pj[t] = p[j];
-        vj[t] = v[j];
-#pragma unroll
-        for (int q = 0; q < RW; ++q) aj[q][t] = row[q][j];
-      }
+    for (int64_t j0 = jr0; j0 < m; j0 += 64 * RB) {
+      if (j0 != jr0) load_rows(j0);
 #pragma unroll
       for (int q = 0; q < RW; ++q) {
         if (q >= nr) break;
@@ -238,7 +264,7 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(double *A, int64_t n,
         for (int t = 0; t < RB; ++t) {
           const int64_t j = j0 + 64 * t;
           if (j < m) {
-            const double a = aj[q][t] - (vi[q] * (pj[t] - K * vj[t]) + wi[q] * vj[t]);
+            const double a = aj[q][t] - (vi[q] * (qj[t] - K * uj[t]) + wi[q] * uj[t]);
             row[q][j] = a;
             acc[q] += a * vn[j - 1];
           }
