@@ -143,13 +143,15 @@ constexpr int64_t kTridiagTwoRows = 1024;   // trailing rows from which a wave t
 // Step k's rank-2 update fused with step k+1's reflector and product, so that
 // the trailing block is read and written once per step.  Row k+1 (row 0 of the
 // step-k trailing block, the source of reflector k+1) is only read: every
-// work-group forms its updated entries itself and stages reflector k+1 in LDS
-// (m - 1 doubles of dynamic shared memory).  The rows and columns k+2 .. of A
+// work-group forms its updated entries itself, with their squared norm in the
+// same pass, and stages them in LDS unscaled (m - 1 doubles of dynamic shared
+// memory; the scale is applied where the reflector is used).  The rows and columns k+2 .. of A
 // (the trailing block of step k+1) are updated in place, one wave per row, and
 // each wave then forms its entry of p = tau A22 v for step k+1; column k+1,
 // which no later step reads, is left as it is.  p and pv of step k are read
-// and those of step k+1 written to separate buffers.  The arithmetic and the
-// summation order are those of house_symv_kernel and rank2_fused_kernel.
+// and those of step k+1 written to separate buffers.  The arithmetic is that of
+// house_symv_kernel and rank2_fused_kernel (the reflector's norm summed in
+// another order); three barriers per step.
 // RW rows of the step-(k+1) block per wave (RW = 2 for large blocks: p and v are
 // loaded once for both rows, and the work-group's own reflector is formed for
 // twice the rows); nparts = the number of partial sums pv written by the launch
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(double *A, int64_t n,
                                                            const double *pv, int64_t nparts,
                                                            double *p1, double *pv1, int *nonfinite) {
   extern __shared__ double vn[];
-  __shared__ double red[4], part[4];
+  __shared__ double red[4], nrm[4], part[4];
   const int64_t m = n - k - 1, m1 = m - 1;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double *v = V + k * n + k + 1;                 // reflector k, v[0] = 1
@@ -220,25 +222,43 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(double *A, int64_t n,
   if (lane == 0) red[wv] = s;
   __syncthreads();
   const double K = 0.5 * tau[k] * (red[0] + red[1] + red[2] + red[3]);
-  __syncthreads();                                     // red is reused below
   const double w0 = p0 - K * v0;
+  // row k+1 after the update (the unscaled reflector, vn[0] = its first entry)
+  // and, in the same pass, its squared norm past the first entry
+  double ss = 0.0;
   for (int64_t j0 = jx0; j0 < m; j0 += 256 * RB) {
     if (j0 != jx0) load_x(j0);
 #pragma unroll
     for (int t = 0; t < RB; ++t) {
       const int64_t j = j0 + 256 * t;
-      if (j < m) vn[j - 1] = xj[t] - (v0 * (pj[t] - K * vj[t]) + w0 * vj[t]);
+      if (j < m) {
+        const double u = xj[t] - (v0 * (pj[t] - K * vj[t]) + w0 * vj[t]);
+        vn[j - 1] = u;
+        if (j >= 2) ss += u * u;
+      }
     }
   }
-  __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) ss += __shfl_down(ss, o, 64);
+  if (lane == 0) nrm[wv] = ss;
+  __syncthreads();                                     // vn and nrm complete
+  // reflector k+1: beta = -sign(alpha) |x|, tau = (beta - alpha)/beta and
+  // v = x/(alpha - beta) with v0 = 1 (tau = 0 when the tail of x is 0); v is
+  // formed where it is used, vs(i) = i == 0 ? 1 : vn[i] * scale
+  const double xn2 = nrm[0] + nrm[1] + nrm[2] + nrm[3], alpha = vn[0];
   double t, scale, beta;
-  reflector(vn, m1, red, t, scale, beta);
-  __syncthreads();                                     // every thread has read vn[0]
-  for (int64_t i = threadIdx.x; i < m1; i += 256) vn[i] = i == 0 ? 1.0 : vn[i] * scale;
-  __syncthreads();
+  if (xn2 == 0.0) {
+    t = 0.0;
+    beta = alpha;
+    scale = 0.0;
+  } else {
+    beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+    t = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  auto vs = [&](int64_t i) -> double { return i == 0 ? 1.0 : vn[i] * scale; };
   if (blockIdx.x == 0) {
     double *vo = V + (k + 1) * n + k + 2;
-    for (int64_t i = threadIdx.x; i < m1; i += 256) vo[i] = vn[i];
+    for (int64_t i = threadIdx.x; i < m1; i += 256) vo[i] = vs(i);
     if (threadIdx.x == 0) {
       if (!isfinite(beta) || !isfinite(t)) atomicExch(nonfinite, 1);
       tau[k + 1] = t;
@@ -266,7 +286,7 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(double *A, int64_t n,
           if (j < m) {
             const double a = aj[q][t] - (vi[q] * (qj[t] - K * uj[t]) + wi[q] * uj[t]);
             row[q][j] = a;
-            acc[q] += a * vn[j - 1];
+            acc[q] += a * vs(j - 1);
           }
         }
       }
@@ -277,7 +297,7 @@ __global__ __launch_bounds__(256) void tridiag_step_kernel(double *A, int64_t n,
       double s = acc[q];
       for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
       const double pi = t * s;
-      pvr += pi * vn[r0 + q];
+      pvr += pi * vs(r0 + q);
       if (lane == 0) p1[r0 + q] = pi;
     }
   }
