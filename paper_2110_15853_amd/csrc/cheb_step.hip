@@ -156,9 +156,9 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_mfma(
   // descriptor's range would return 0 instead of faulting.
   const int32_t yoff = (int32_t)(((int64_t)krow * ldk + colc) * (int64_t)sizeof(T));
   const int32_t panel_bytes = (int32_t)(64 * ldk * (int64_t)sizeof(T));
-  auto load_b = [&](int t, int qq, T (&dst)[4]) {
+  auto load_b = [&](int64_t brow, int qq, T (&dst)[4]) {   // quarter qq of panel brow
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(Yk + (int64_t)tcol[t] * 64 * ldk), 0, panel_bytes, kBufferWord3);
+        (void *)(Yk + brow * 64 * ldk), 0, panel_bytes, kBufferWord3);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       dst[q] = buffer_load<T>(rs, yoff, (int32_t)((16 * qq + 4 * q) * ldk * (int64_t)sizeof(T)));
@@ -179,28 +179,34 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_mfma(
   };
   auto tile_mask = [&](int t) -> uint64_t { return frag_mask ? frag_mask[t] : ~0ull; };
   // one tile: contract `cur`, meanwhile move tile tn into `nxt` and its Y_k panel
-  // into b0..b3 (each quarter refilled once contracted)
+  // into b0..b3 (each quarter refilled once contracted).  FP64: after the last
+  // tile the refill is the work-group's own panel Y_k[B], whose quarters are in
+  // the layout of the f64 op's accumulators (row 16 qq + 4 q + l/16 of the panel
+  // is item q of accumulator qq), so the epilogue does not wait for it; the f32
+  // op's accumulator rows are 4 (l/16) + q, so FP32 loads its values there.
+  constexpr bool kOwnPanel = sizeof(T) == 8;
   auto step = [&](int t, const T *cur, T *nxt, uint64_t fm) {
     const int tn = min(t + 1, t_end - 1);   // t may be t_end (empty step)
-    dma_h(tn, nxt);
+    const int64_t pn = kOwnPanel && t + 1 >= t_end ? B : (int64_t)tcol[tn];
+    if (t + 1 < t_end) dma_h(tn, nxt);       // no tile after the last one
     mma_quarter(cur, 0, b0, fm);
-    load_b(tn, 0, b0);
+    load_b(pn, 0, b0);
     mma_quarter(cur, 1, b1, fm);
-    load_b(tn, 1, b1);
+    load_b(pn, 1, b1);
     mma_quarter(cur, 2, b2, fm);
-    load_b(tn, 2, b2);
+    load_b(pn, 2, b2);
     mma_quarter(cur, 3, b3, fm);
-    load_b(tn, 3, b3);
+    load_b(pn, 3, b3);
     wait_vmcnt<16>();      // this wave's transfers of tile tn are in LDS
     __syncthreads();
   };
 
   if (t_begin < t_end) {
     dma_h(t_begin, sH0);
-    load_b(t_begin, 0, b0);
-    load_b(t_begin, 1, b1);
-    load_b(t_begin, 2, b2);
-    load_b(t_begin, 3, b3);
+    load_b(tcol[t_begin], 0, b0);
+    load_b(tcol[t_begin], 1, b1);
+    load_b(tcol[t_begin], 2, b2);
+    load_b(tcol[t_begin], 3, b3);
     wait_vmcnt<16>();
     __syncthreads();
     // tiles in pairs (the two LDS buffers stay distinct objects, so the compiler
@@ -215,13 +221,24 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_mfma(
     }
   }
 
-  // epilogue: loads first, then the stores
+  // epilogue: Y_k[B] (FP64: from the last refill, unless the row has no tiles),
+  // Y_{k-1}[B], then the stores
   T yk[4][4], yp[4][4];
+  if (kOwnPanel && t_begin < t_end) {
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+    for (int q = 0; q < 4; ++q) {
+      yk[0][q] = b0[q];
+      yk[1][q] = b1[q];
+      yk[2][q] = b2[q];
+      yk[3][q] = b3[q];
+    }
+  } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      yk[mb][q] = Yk[(B * 64 + 16 * mb + M::row(lane, q)) * ldk + colc];
+    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        yk[mb][q] = Yk[(B * 64 + 16 * mb + M::row(lane, q)) * ldk + colc];
+  }
   if (beta != T(0)) {
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
