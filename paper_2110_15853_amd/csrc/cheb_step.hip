@@ -186,7 +186,7 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_mfma(
   // op's accumulator rows are 4 (l/16) + q, so FP32 loads its values there.
   constexpr bool kOwnPanel = sizeof(T) == 8;
   auto step = [&](int t, const T *cur, T *nxt, uint64_t fm) {
-    const int tn = min(t + 1, t_end - 1);   // t may be t_end (empty step)
+    const int tn = min(t + 1, t_end - 1);
     const int64_t pn = kOwnPanel && t + 1 >= t_end ? B : (int64_t)tcol[tn];
     if (t + 1 < t_end) dma_h(tn, nxt);       // no tile after the last one
     mma_quarter(cur, 0, b0, fm);
@@ -211,14 +211,16 @@ __global__ __launch_bounds__(F64_THREADS, 4) void cheb_step_mfma(
     __syncthreads();
     // tiles in pairs (the two LDS buffers stay distinct objects, so the compiler
     // can tell the transfer into one from the reads of the other); an odd last
-    // tile is paired with an empty step (mask 0: no products)
+    // tile, already in sH0, takes one step of its own
     uint64_t fm = tile_mask(t_begin);
-    for (int t = t_begin; t < t_end; t += 2) {
-      const uint64_t fm1 = t + 1 < t_end ? tile_mask(t + 1) : 0ull;
+    int t = t_begin;
+    for (; t + 1 < t_end; t += 2) {
+      const uint64_t fm1 = tile_mask(t + 1);
       step(t, sH0, sH1, fm);
       fm = t + 2 < t_end ? tile_mask(t + 2) : 0ull;
       step(t + 1, sH1, sH0, fm1);
     }
+    if (t < t_end) step(t, sH0, sH1, fm);
   }
 
   // epilogue: Y_k[B] (FP64: from the last refill, unless the row has no tiles),
