@@ -199,6 +199,17 @@ def mixed_precision_report(P, torch, ip, ix, d, cfg, H64, Xb64, keep_frac=1800 /
     return out
 
 
+def symmetric_formed_tiles(rowptr, tcol):
+    """Tiles a symmetric sampled product forms (P = P^T: each mirror pair once):
+    (B, B') with B' >= B, and those with B' < B whose mirror (B', B) is not stored."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    nbr = len(rowptr) - 1
+    brow = np.repeat(np.arange(nbr, dtype=np.int64), np.diff(rowptr))
+    bcol = np.asarray(tcol, dtype=np.int64)
+    mirrored = np.isin(bcol * nbr + brow, brow * nbr + bcol)
+    return (bcol >= brow) | ~mirrored
+
+
 def density_report(P, torch, H, lam, psi, cfg):
     """Occupancies at the paper's smearing temperature (500 K) for N_e = 1.5 n
     electrons, the density matrix on the pattern of H and the site density,
@@ -220,14 +231,9 @@ def density_report(P, torch, H, lam, psi, cfg):
     tr = float((Pv * H.vals).sum())
     want = 2.0 * float((f * lam).sum())
     # the sampled product issues 2 * 256 * n flop per 16 x 16 block that holds a
-    # pattern entry (the other blocks are skipped), over the tiles it forms: P is
-    # symmetric, so the tiles (B, B') with B' >= B and those whose mirror is not stored
+    # pattern entry (the other blocks are skipped), over the tiles it forms
     m = H.mask.view(H.n_tiles, 4, 16).cpu().numpy().view(np.uint64)
-    rowptr = H.tile_rowptr.cpu().numpy()
-    brow = np.repeat(np.arange(H.n_block_rows, dtype=np.int64), np.diff(rowptr))
-    bcol = H.tile_col.cpu().numpy().astype(np.int64)
-    mirrored = np.isin(bcol * H.n_block_rows + brow, brow * H.n_block_rows + bcol)
-    formed = (bcol >= brow) | ~mirrored
+    formed = symmetric_formed_tiles(H.tile_rowptr.cpu().numpy(), H.tile_col.cpu().numpy())
     rows_or = np.bitwise_or.reduce(m[formed], axis=2)               # [formed tile, row block]
     live = sum(int(np.count_nonzero((rows_or >> np.uint64(16 * jb)) & np.uint64(0xFFFF)))
                for jb in range(4))
